@@ -1,0 +1,225 @@
+/*
+ * transims.h -- C ABI of libtransims, the MI355X (gfx950) implementation of
+ * the per-second cellular-automaton update of the TRANSIMS micro-simulation
+ * (K. Nagel, M. Rickert, "Parallel implementation of the TRANSIMS
+ * micro-simulation").
+ *
+ * One step moves every vehicle on every link of a scenario by one second
+ * (Section "Microsimulation driving logic"): 7.5 m cells holding at most one
+ * vehicle, integer speeds 0..vmax cells per step, accelerate / brake to the
+ * gap / random slowdown / move (rules i-iii), a lane-change sub-step before
+ * the forward move, unsignalised intersections with priority (gap acceptance
+ * on the priority street), and vehicles entering from and exiting to parking
+ * along precomputed routes.  The update order follows the paper's sequence
+ * "change lanes, exchange boundaries, compute speeds and move, exchange"
+ * (Section "Micro-simulation parallelization: Domain decomposition"); on one
+ * GPU the two boundary exchanges become kernel boundaries plus in-memory
+ * handoff slots.
+ *
+ * Rules the paper leaves open are fixed as follows (the same readings bind
+ * every implementation that claims to compute this step):
+ *   - speeds: v1 = min(v+1, vmax); v2 = min(v1, gap); v3 = v2-1 when v2 > 0
+ *     and the vehicle's draw u < slow_thr, else v2; x' = x + v3;
+ *   - draws: word 0 of Philox4x32-10 under key (seed lo, seed hi) at counter
+ *     (vehicle id, t, sub-step, 0), sub-step 0 = lane change, 1 = slowdown;
+ *   - parking: at most one vehicle per link per step enters cell 0 of the
+ *     lowest lane whose cell 0 is empty, FIFO by (depart, id);
+ *   - lane change: incentive + gap checks of vmax cells; turn lanes shrink
+ *     the accepted gap toward the node; two movers into one cell: the one
+ *     from the lower lane moves;
+ *   - intersections: the lead vehicle of a lane within vmax cells of the
+ *     node aims at lane min(k, lanes'-1) of its next link; per target lane
+ *     the smallest (rank, lane) wins and may drive min(vmax, x_rear) cells
+ *     into the next link; losers stop at the link end; a trip ends at the
+ *     end of the last link (extra = vmax).
+ * Every step is integer; results are bit-identical to the CPU oracle.
+ *
+ * Threading: one context per host thread.  All device work of a context runs
+ * on the stream given at creation.  No exception crosses this boundary.
+ */
+#ifndef TRANSIMS_H
+#define TRANSIMS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SIM_ABI_VERSION 1
+
+typedef enum {
+  SIM_OK = 0,
+  SIM_E_INVAL = -1,    /* invalid argument or inconsistent input data        */
+  SIM_E_NOMEM = -2,    /* the caller's workspace is smaller than needed      */
+  SIM_E_STATE = -3,    /* wrong call order, or slot not loaded               */
+  SIM_E_DEVICE = -4,   /* HIP runtime error, or sticky device error bits     */
+  SIM_E_CAPACITY = -5, /* a size exceeds a library limit                     */
+  SIM_E_ABI = -6       /* abi_version mismatch                               */
+} sim_status;
+
+/* scenario flags */
+#define SIM_FLAG_RING 1u        /* one periodic lane, no nodes, no parking    */
+#define SIM_FLAG_LANE_CHANGE 2u /* lane-change sub-step on multi-lane links   */
+#define SIM_FLAG_TURN_LANES 4u  /* lane changes toward the lanes of the turn  */
+
+/* device error bits reported in sim_stats_t.dev_err */
+#define SIM_DEVERR_LANE_FULL 1u /* a lane received more vehicles than cells   */
+
+typedef struct sim_ctx sim_ctx;
+
+typedef struct {
+  int32_t abi_version; /* must be SIM_ABI_VERSION                           */
+  int32_t max_slots;   /* number of independent scenario slots (>= 1)       */
+  void* stream;        /* hipStream_t for all device work; NULL = default   */
+  int32_t tile_lanes;  /* lanes per workgroup tile, 1..64; 0 = default (16) */
+  int32_t reserved;
+} sim_config;
+
+/* Per-scenario parameters. */
+typedef struct {
+  uint32_t flags;
+  int32_t vmax;      /* 1..7 cells per step (5 = 135 km/h)                   */
+  uint64_t slow_thr; /* slowdown iff draw < slow_thr; floor(p*2^32), <= 2^32 */
+  uint64_t lc_thr;   /* discretionary lane change iff draw < lc_thr, <= 2^32 */
+  int32_t lc_desp;   /* desperation distance D (cells) for turn lanes, >= 1  */
+  uint64_t seed;     /* Philox key                                          */
+} sim_params;
+
+/* Road network, borrowed for the duration of the call (copied). */
+typedef struct {
+  int32_t n_nodes;
+  int32_t n_links;
+  const int32_t* from;  /* [n_links] upstream node                         */
+  const int32_t* to;    /* [n_links] downstream node (!= from)              */
+  const int32_t* len;   /* [n_links] cells; vmax+1..32767 (ring: 1..32767) */
+  const int8_t* lanes;  /* [n_links] 1..4; lane 0 is the leftmost          */
+  const int8_t* rank;   /* [n_links] 0..127, priority among the links that
+                           enter one node (0 first); unique per node        */
+  /* lane connectivity, needed with SIM_FLAG_TURN_LANES, else may be NULL:
+     entries conn_off[l]..conn_off[l+1]-1 name an out-link of to[l] and the
+     lanes [lo, hi] of l from which that turn is made                       */
+  const int64_t* conn_off;
+  const int32_t* conn_out;
+  const int8_t* conn_lo;
+  const int8_t* conn_hi;
+  const double* node_xy;   /* optional [2*n_nodes]; used only for tiling     */
+  const float* link_cost;  /* optional [n_links] tiling weights (e.g. costs
+                              measured by sim_link_costs on an earlier run)  */
+} sim_network;
+
+/* Travellers and their plans, borrowed for the duration of the call.
+   Vehicle id = index.  A vehicle whose status is WAITING enters from parking
+   at the first link of its route at step depart or later. */
+typedef struct {
+  int32_t n;
+  const int32_t* depart;      /* [n]                                        */
+  const int64_t* route_off;   /* [n+1]; NULL in ring mode                   */
+  const int32_t* route_links; /* [route_off[n]]; consecutive links connect  */
+  /* optional initial state; all NULL = every vehicle WAITING              */
+  const int8_t* init_status;  /* 0 WAITING, 1 ACTIVE, 2 ARRIVED             */
+  const int8_t* init_lane;    /* ACTIVE: lane                               */
+  const int32_t* init_x;      /* ACTIVE: cell                               */
+  const int8_t* init_v;       /* ACTIVE: speed 0..vmax                      */
+  const int32_t* init_rptr;   /* ACTIVE: route index of the current link    */
+  const int32_t* exit_t0;     /* [route_off[n]] or NULL (= all -1)          */
+  int32_t t0;                 /* index of the first step                    */
+} sim_vehicles;
+
+typedef struct {
+  int32_t t; /* index of the next step                                      */
+  int32_t reserved;
+  int64_t n_waiting, n_active, n_arrived;
+  int64_t veh_updates;  /* sum over steps of vehicles moved               */
+  int64_t sum_v;        /* sum over all updates of the new speed           */
+  int64_t crossings;    /* moves onto the next link of a route             */
+  int64_t exits;        /* trips ended                                     */
+  int64_t lane_changes;
+  int64_t insertions;
+  int64_t c_occ;        /* sum over steps of cells in lanes holding a car  */
+  uint64_t hash;        /* order-independent hash of the current state     */
+  uint32_t dev_err;     /* SIM_DEVERR_* bits                               */
+  uint32_t reserved2;
+} sim_stats_t;
+
+/* Creates a context on the current HIP device.  *out receives it. */
+sim_status sim_create(const sim_config* cfg, sim_ctx** out);
+
+/* Bytes of device workspace that sim_load_network + sim_load_vehicles need
+   for this scenario (the caller allocates them, e.g. as a torch tensor). */
+sim_status sim_footprint(const sim_ctx* ctx, const sim_params* p,
+                         const sim_network* net, const sim_vehicles* veh,
+                         uint64_t* bytes);
+
+/* Loads a network into `slot`, tiling its links onto workgroups (orthogonal
+   recursive bisection over link midpoints, weighted by cells or by
+   net->link_cost).  dev_ws is device memory owned by the caller that must
+   stay valid until sim_unload; the library never frees it.  Any scenario
+   previously in the slot is unloaded. */
+sim_status sim_load_network(sim_ctx* ctx, int32_t slot, const sim_params* p,
+                            const sim_network* net, void* dev_ws,
+                            uint64_t ws_bytes);
+
+/* Loads vehicles and routes into a slot holding a network.  Synchronises
+   the context stream before returning. */
+sim_status sim_load_vehicles(sim_ctx* ctx, int32_t slot,
+                             const sim_vehicles* veh);
+
+/* Enqueues n_steps steps of every listed slot on the context stream and
+   returns without waiting.  The slots advance together in one launch per
+   sub-step; they never interact. */
+sim_status sim_step(sim_ctx* ctx, const int32_t* slots, int32_t n_slots,
+                    int32_t n_steps);
+
+/* Waits for the stream and reports the slot's counters and state hash.
+   Returns SIM_E_DEVICE (with out filled) if device error bits are set. */
+sim_status sim_stats(sim_ctx* ctx, int32_t slot, sim_stats_t* out);
+
+/* Waits for the stream and copies the per-vehicle state to host arrays of
+   n entries (any may be NULL): status, link (-1 unless ACTIVE), lane, x, v,
+   rptr; exit_t receives route_off[n] entries. */
+sim_status sim_read_state(sim_ctx* ctx, int32_t slot, int8_t* status,
+                          int32_t* link, int8_t* lane, int32_t* x, int8_t* v,
+                          int32_t* rptr, int32_t* exit_t);
+
+/* Measured cost per link (device clock cycles spent on the link's tile,
+   shared out by cells), for use as net->link_cost of a later run (adaptive
+   load balancing). out has n_links entries. */
+sim_status sim_link_costs(sim_ctx* ctx, int32_t slot, float* out);
+
+typedef struct {
+  int32_t n_tiles;
+  int32_t n_lanes;
+  int64_t n_cells;
+  double e_dmn;      /* mean / max tile weight over the 8 XCD domains      */
+  double e_tile;     /* mean / max weight over tiles                       */
+} sim_tiling;
+
+sim_status sim_tiling_info(const sim_ctx* ctx, int32_t slot, sim_tiling* out);
+
+/* Kernel timing (the paper monitors the time per step): while enabled,
+   sim_step brackets every kernel launch with HIP events on the context
+   stream.  sim_kernel_times waits for the stream, reports per kernel kind
+   (0 = front/lane-change sub-step, 1 = back/move sub-step, 2 = ring) the
+   number of launches and their summed duration, and resets the sums. */
+typedef struct {
+  int64_t launches;
+  double total_ms;
+} sim_kernel_time;
+
+sim_status sim_profile(sim_ctx* ctx, int32_t enable);
+sim_status sim_kernel_times(sim_ctx* ctx, sim_kernel_time out[3]);
+
+/* Forgets the slot (its workspace may then be released by the caller). */
+sim_status sim_unload(sim_ctx* ctx, int32_t slot);
+
+/* Destroys the context and its library-owned device and host memory. */
+sim_status sim_destroy(sim_ctx* ctx);
+
+/* Text of the last error on this context ("" if none). */
+const char* sim_last_error(const sim_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

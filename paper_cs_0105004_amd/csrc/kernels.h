@@ -1,0 +1,41 @@
+// kernels.h -- launchers of the libtransims device kernels (host side).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "layout.h"
+
+namespace tr {
+
+// One step of every tile in `work` ({slot, tile} pairs, in dispatch order):
+// the front kernel merges arrivals, lets vehicles leave parking, runs the
+// lane-change sub-step and publishes per-lane summaries; the back kernel
+// resolves the intersections and moves every vehicle (second sub-step).
+// lc_cells: largest lanes*len over links that change lanes (LDS lattice).
+hipError_t launch_front(const DevScen* d_descs, const int2* d_work, int n_work,
+                        int step, int lc_cells, hipStream_t s);
+hipError_t launch_back(const DevScen* d_descs, const int2* d_work, int n_work,
+                       int step, hipStream_t s);
+// descs[slots[i]].t += k for i < n
+hipError_t launch_advance(DevScen* d_descs, const int* d_slots, int n, int k,
+                          hipStream_t s);
+// All n_steps of each listed ring slot in one launch (one workgroup each).
+hipError_t launch_ring(DevScen* d_descs, const int* d_slots, int n,
+                       int n_steps, hipStream_t s);
+// out[0..C_N) counter sums, out[C_N] active, out[C_N+1] hash,
+// out[C_N+2] waiting; out must be zeroed first.
+hipError_t launch_stats(const DevScen* d_desc, unsigned long long* d_out,
+                        int ring, hipStream_t s);
+
+struct ExportBufs {
+  int8_t* status;
+  int32_t* link;
+  int8_t* lane;
+  int32_t* x;
+  int8_t* v;
+  int32_t* rptr;
+};
+hipError_t launch_export(const DevScen* d_desc, ExportBufs out, int n_veh,
+                         int n_links, int n_lanes, int ring, hipStream_t s);
+
+}  // namespace tr

@@ -1,0 +1,952 @@
+// transims.cpp -- host side of libtransims: input checks, link tiling,
+// device layout, launches.  See include/transims.h for the contract.
+#include "../../include/transims.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "kernels.h"
+#include "layout.h"
+#include "tiler.h"
+
+using namespace tr;
+
+namespace {
+
+constexpr int kLcMaxLen = 2048;  // longest multi-lane link that changes lanes
+constexpr int kDefaultTileLanes = 16;
+
+struct Slot {
+  bool net = false, veh = false, ring = false;
+  sim_params p{};
+  int32_t n_nodes = 0, n_links = 0, n_lanes = 0, n_tiles = 0, n_veh = 0;
+  int64_t n_route = 0, n_records = 0, n_cells = 0;
+  std::vector<int32_t> ext_of, int_of;  // internal <-> caller link ids
+  std::vector<int32_t> len, lanes, lane0, from, to;  // internal order
+  std::vector<int2> tiles;
+  std::vector<double> weight;  // internal order
+  uint8_t* ws = nullptr;
+  uint64_t ws_bytes = 0, ws_net = 0;
+  DevScen d{};
+  int32_t t = 0;
+  int32_t lc_cells = 0;
+  sim_tiling tiling{};
+};
+
+}  // namespace
+
+struct sim_ctx {
+  sim_config cfg{};
+  hipStream_t stream = nullptr;
+  int device = 0;
+  std::vector<Slot> slots;
+  DevScen* d_descs = nullptr;
+  int2* d_work = nullptr;
+  size_t work_cap = 0;
+  int* d_list = nullptr;  // network slots, then ring slots
+  size_t list_cap = 0;
+  unsigned long long* d_stats = nullptr;
+  std::vector<int32_t> work_key;
+  int n_work = 0, n_net = 0, n_ring = 0, lc_cells = 0;
+  // kernel timing
+  bool profile = false;
+  std::vector<hipEvent_t> events;  // pairs around launches
+  std::vector<int> event_kind;     // kind of each pair
+  size_t n_pairs = 0;
+  std::string err;
+};
+
+namespace {
+
+sim_status fail(sim_ctx* c, sim_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (c) c->err = buf;
+  return st;
+}
+
+#define HIPCHK(ctx, expr)                                                   \
+  do {                                                                      \
+    hipError_t e_ = (expr);                                                 \
+    if (e_ != hipSuccess)                                                   \
+      return fail(ctx, SIM_E_DEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+// Bump allocator over the caller's workspace; with base == nullptr it only
+// measures.
+struct Carve {
+  uint8_t* base;
+  uint64_t off;
+  template <class T>
+  T* take(int64_t n) {
+    off = (off + 255) & ~uint64_t(255);
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += (uint64_t)std::max<int64_t>(n, 1) * sizeof(T);
+    return p;
+  }
+};
+
+bool lc_link(const sim_params& p, int lanes) {
+  return (p.flags & SIM_FLAG_LANE_CHANGE) && lanes >= 2;
+}
+
+struct NetDims {
+  int64_t L, Q, rec, nodes, conn;
+};
+
+// device arrays of the network part; pointers are null when measuring
+void carve_network(Carve& cv, const NetDims& nd, DevScen& d, bool ring) {
+  const int64_t L = nd.L, Q = nd.Q;
+  d.link_len = cv.take<int32_t>(L);
+  d.link_lanes = cv.take<int8_t>(L);
+  d.link_lane0 = cv.take<int32_t>(L);
+  d.link_to = cv.take<int32_t>(L);
+  d.link_rank = cv.take<int8_t>(L);
+  d.link_ext = cv.take<int32_t>(L);
+  d.node_in_off = cv.take<int32_t>(nd.nodes + 1);
+  d.node_in = cv.take<int32_t>(L);
+  d.conn_off = cv.take<int32_t>(L + 1);
+  d.conn_out = cv.take<int32_t>(nd.conn);
+  d.conn_lo = cv.take<int8_t>(nd.conn);
+  d.conn_hi = cv.take<int8_t>(nd.conn);
+  d.lane_link = cv.take<int32_t>(Q);
+  d.lane_base = cv.take<int32_t>(Q);
+  d.lane_hc = cv.take<int2>(Q);
+  d.lane_sum = cv.take<int2>(Q);
+  d.hand_a = cv.take<int4>(Q);
+  d.hand_nxt = cv.take<int32_t>(Q);
+  d.hot = cv.take<uint2>(ring ? 0 : nd.rec);
+  d.cold = cv.take<int2>(ring ? 0 : nd.rec);
+  d.tile_lanes = cv.take<int2>(Q);  // at most one tile per lane
+  d.tile_ctr = cv.take<long long>(Q * C_N);
+  d.wait_off = cv.take<int32_t>(L + 1);
+  d.wait_head = cv.take<int32_t>(L);
+  d.ring_ctr = cv.take<long long>(C_N);
+  d.err = cv.take<uint32_t>(1);
+}
+
+void carve_vehicles(Carve& cv, int64_t n, int64_t R, DevScen& d, bool ring) {
+  d.wait_id = cv.take<int32_t>(ring ? 0 : n);
+  d.wait_dep = cv.take<int32_t>(ring ? 0 : n);
+  d.route_off = cv.take<int64_t>(ring ? 0 : n + 1);
+  d.route_links = cv.take<int32_t>(R);
+  d.exit_t = cv.take<int32_t>(R);
+  d.ring_x = cv.take<int32_t>(ring ? n : 0);
+  d.ring_v = cv.take<int32_t>(ring ? n : 0);
+  d.ring_id = cv.take<int32_t>(ring ? n : 0);
+}
+
+sim_status check_params(sim_ctx* c, const sim_params* p) {
+  if (!p) return fail(c, SIM_E_INVAL, "params is NULL");
+  if (p->vmax < 1 || p->vmax > 7) return fail(c, SIM_E_INVAL, "vmax must be 1..7");
+  if (p->slow_thr > (1ull << 32) || p->lc_thr > (1ull << 32))
+    return fail(c, SIM_E_INVAL, "thresholds must be <= 2^32");
+  if (p->lc_desp < 1) return fail(c, SIM_E_INVAL, "lc_desp must be >= 1");
+  if (p->flags & ~(SIM_FLAG_RING | SIM_FLAG_LANE_CHANGE | SIM_FLAG_TURN_LANES))
+    return fail(c, SIM_E_INVAL, "unknown flag bits");
+  return SIM_OK;
+}
+
+sim_status check_network(sim_ctx* c, const sim_params* p, const sim_network* n) {
+  if (!n) return fail(c, SIM_E_INVAL, "network is NULL");
+  const bool ring = p->flags & SIM_FLAG_RING;
+  if (n->n_links < 1) return fail(c, SIM_E_INVAL, "need at least one link");
+  if (!n->len || !n->lanes || (!ring && (!n->from || !n->to || !n->rank)))
+    return fail(c, SIM_E_INVAL, "missing link arrays");
+  if (ring) {
+    if (n->n_links != 1 || n->lanes[0] != 1)
+      return fail(c, SIM_E_INVAL, "ring mode needs one single-lane link");
+    if (n->len[0] < 1 || n->len[0] > 32767)
+      return fail(c, SIM_E_INVAL, "ring length must be 1..32767");
+    return SIM_OK;
+  }
+  if (n->n_nodes < 1) return fail(c, SIM_E_INVAL, "need nodes");
+  std::vector<uint8_t> seen((size_t)n->n_nodes * 128, 0);
+  for (int32_t l = 0; l < n->n_links; ++l) {
+    if (n->lanes[l] < 1 || n->lanes[l] > 4)
+      return fail(c, SIM_E_INVAL, "link %d: lanes must be 1..4", l);
+    if (n->len[l] < p->vmax + 1 || n->len[l] > 32767)
+      return fail(c, SIM_E_INVAL, "link %d: length must be vmax+1..32767", l);
+    if (n->from[l] < 0 || n->from[l] >= n->n_nodes || n->to[l] < 0 ||
+        n->to[l] >= n->n_nodes)
+      return fail(c, SIM_E_INVAL, "link %d: node out of range", l);
+    if (n->from[l] == n->to[l])
+      return fail(c, SIM_E_INVAL, "link %d is a self-loop", l);
+    if (n->rank[l] < 0) return fail(c, SIM_E_INVAL, "link %d: negative rank", l);
+    uint8_t& f = seen[(size_t)n->to[l] * 128 + (size_t)n->rank[l]];
+    if (f)
+      return fail(c, SIM_E_INVAL, "two links enter node %d with rank %d",
+                  n->to[l], n->rank[l]);
+    f = 1;
+    if (lc_link(*p, n->lanes[l]) && n->len[l] > kLcMaxLen)
+      return fail(c, SIM_E_CAPACITY,
+                  "link %d: lane changing supports links up to %d cells", l,
+                  kLcMaxLen);
+  }
+  if (p->flags & SIM_FLAG_TURN_LANES) {
+    if (!n->conn_off || !n->conn_out || !n->conn_lo || !n->conn_hi)
+      return fail(c, SIM_E_INVAL, "turn lanes need the lane connectivity table");
+    if (n->conn_off[0] != 0)
+      return fail(c, SIM_E_INVAL, "conn_off[0] must be 0");
+    for (int32_t l = 0; l < n->n_links; ++l) {
+      if (n->conn_off[l + 1] < n->conn_off[l])
+        return fail(c, SIM_E_INVAL, "conn_off must not decrease");
+      for (int64_t e = n->conn_off[l]; e < n->conn_off[l + 1]; ++e) {
+        const int32_t o = n->conn_out[e];
+        if (o < 0 || o >= n->n_links || n->from[o] != n->to[l])
+          return fail(c, SIM_E_INVAL, "link %d: bad connectivity entry", l);
+        if (n->conn_lo[e] < 0 || n->conn_lo[e] > n->conn_hi[e] ||
+            n->conn_hi[e] >= n->lanes[l])
+          return fail(c, SIM_E_INVAL, "link %d: bad turn lanes", l);
+      }
+    }
+    if (n->conn_off[n->n_links] > INT32_MAX)
+      return fail(c, SIM_E_CAPACITY, "connectivity table too large");
+  }
+  return SIM_OK;
+}
+
+NetDims net_dims(const sim_params* p, const sim_network* n) {
+  NetDims nd{n->n_links, 0, 0, std::max(n->n_nodes, 1), 0};
+  for (int32_t l = 0; l < n->n_links; ++l) {
+    nd.Q += n->lanes[l];
+    nd.rec += (int64_t)n->lanes[l] * n->len[l] * (lc_link(*p, n->lanes[l]) ? 2 : 1);
+  }
+  if ((p->flags & SIM_FLAG_TURN_LANES) && n->conn_off) nd.conn = n->conn_off[n->n_links];
+  return nd;
+}
+
+sim_status check_slot(sim_ctx* c, int32_t slot) {
+  if (!c) return SIM_E_INVAL;
+  if (slot < 0 || slot >= (int32_t)c->slots.size())
+    return fail(c, SIM_E_INVAL, "slot %d out of range", slot);
+  return SIM_OK;
+}
+
+template <class T>
+hipError_t up(T* dst, const T* src, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  return hipMemcpyAsync(dst, src, (size_t)n * sizeof(T), hipMemcpyHostToDevice, s);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+
+extern "C" sim_status sim_create(const sim_config* cfg, sim_ctx** out) {
+  if (!cfg || !out) return SIM_E_INVAL;
+  *out = nullptr;
+  if (cfg->abi_version != SIM_ABI_VERSION) return SIM_E_ABI;
+  if (cfg->max_slots < 1 || cfg->max_slots > 65536) return SIM_E_INVAL;
+  if (cfg->tile_lanes < 0 || cfg->tile_lanes > kMaxTileLanes) return SIM_E_INVAL;
+  sim_ctx* c = new (std::nothrow) sim_ctx();
+  if (!c) return SIM_E_CAPACITY;
+  c->cfg = *cfg;
+  if (c->cfg.tile_lanes == 0) c->cfg.tile_lanes = kDefaultTileLanes;
+  c->stream = reinterpret_cast<hipStream_t>(cfg->stream);
+  c->slots.resize(cfg->max_slots);
+  if (hipGetDevice(&c->device) != hipSuccess ||
+      hipMalloc(&c->d_descs, sizeof(DevScen) * cfg->max_slots) != hipSuccess ||
+      hipMalloc(&c->d_stats, sizeof(unsigned long long) * (C_N + 3)) !=
+          hipSuccess) {
+    sim_destroy(c);
+    return SIM_E_DEVICE;
+  }
+  *out = c;
+  return SIM_OK;
+}
+
+extern "C" sim_status sim_destroy(sim_ctx* c) {
+  if (!c) return SIM_E_INVAL;
+  if (c->stream || c->d_descs) (void)hipStreamSynchronize(c->stream);
+  for (hipEvent_t e : c->events) (void)hipEventDestroy(e);
+  if (c->d_descs) (void)hipFree(c->d_descs);
+  if (c->d_stats) (void)hipFree(c->d_stats);
+  if (c->d_work) (void)hipFree(c->d_work);
+  if (c->d_list) (void)hipFree(c->d_list);
+  delete c;
+  return SIM_OK;
+}
+
+extern "C" const char* sim_last_error(const sim_ctx* c) {
+  return c ? c->err.c_str() : "no context";
+}
+
+extern "C" sim_status sim_footprint(const sim_ctx* cc, const sim_params* p,
+                                    const sim_network* net,
+                                    const sim_vehicles* veh, uint64_t* bytes) {
+  sim_ctx* c = const_cast<sim_ctx*>(cc);
+  if (!bytes) return fail(c, SIM_E_INVAL, "bytes is NULL");
+  sim_status st = check_params(c, p);
+  if (st != SIM_OK) return st;
+  if ((st = check_network(c, p, net)) != SIM_OK) return st;
+  const bool ring = p->flags & SIM_FLAG_RING;
+  DevScen d{};
+  Carve cv{nullptr, 0};
+  carve_network(cv, net_dims(p, net), d, ring);
+  if (veh) {
+    if (veh->n < 0) return fail(c, SIM_E_INVAL, "negative vehicle count");
+    const int64_t R = (!ring && veh->route_off) ? veh->route_off[veh->n] : 0;
+    carve_vehicles(cv, veh->n, R, d, ring);
+  }
+  *bytes = cv.off + 256;
+  return SIM_OK;
+}
+
+extern "C" sim_status sim_load_network(sim_ctx* c, int32_t slot,
+                                       const sim_params* p,
+                                       const sim_network* net, void* dev_ws,
+                                       uint64_t ws_bytes) {
+  sim_status st = check_slot(c, slot);
+  if (st != SIM_OK) return st;
+  if ((st = check_params(c, p)) != SIM_OK) return st;
+  if ((st = check_network(c, p, net)) != SIM_OK) return st;
+  if (!dev_ws) return fail(c, SIM_E_INVAL, "workspace is NULL");
+  Slot& S = c->slots[slot];
+  S = Slot();
+  S.p = *p;
+  S.ring = p->flags & SIM_FLAG_RING;
+  const int32_t L = net->n_links;
+  S.n_links = L;
+  S.n_nodes = S.ring ? 1 : net->n_nodes;
+
+  // ---- tiling: ORB order of links, then whole links packed into tiles
+  std::vector<double> w(L);
+  for (int32_t l = 0; l < L; ++l)
+    w[l] = net->link_cost ? std::max(0.0f, net->link_cost[l])
+                          : (double)net->len[l] * net->lanes[l];
+  std::vector<int32_t> order(L);
+  std::iota(order.begin(), order.end(), 0);
+  if (!S.ring && net->node_xy) {
+    std::vector<double> mx(L), my(L);
+    for (int32_t l = 0; l < L; ++l) {
+      mx[l] = 0.5 * (net->node_xy[2 * net->from[l]] + net->node_xy[2 * net->to[l]]);
+      my[l] = 0.5 * (net->node_xy[2 * net->from[l] + 1] +
+                     net->node_xy[2 * net->to[l] + 1]);
+    }
+    orb_order(order, mx, my, w);
+  }
+  S.ext_of = order;
+  S.int_of.assign(L, 0);
+  for (int32_t i = 0; i < L; ++i) S.int_of[order[i]] = i;
+  S.len.resize(L);
+  S.lanes.resize(L);
+  S.lane0.resize(L);
+  S.from.resize(L);
+  S.to.resize(L);
+  S.weight.resize(L);
+  int32_t q = 0;
+  for (int32_t i = 0; i < L; ++i) {
+    const int32_t e = order[i];
+    S.len[i] = net->len[e];
+    S.lanes[i] = net->lanes[e];
+    S.lane0[i] = q;
+    S.from[i] = S.ring ? 0 : net->from[e];
+    S.to[i] = S.ring ? 0 : net->to[e];
+    S.weight[i] = w[e];
+    q += S.lanes[i];
+    S.n_cells += (int64_t)S.len[i] * S.lanes[i];
+  }
+  S.n_lanes = q;
+  S.tiles = pack_tiles(S.lanes, c->cfg.tile_lanes);
+  S.n_tiles = (int32_t)S.tiles.size();
+  S.tiling = tiling_metrics(S.tiles, S.lanes, S.lane0, S.weight);
+  S.tiling.n_lanes = S.n_lanes;
+  S.tiling.n_cells = S.n_cells;
+
+  // ---- host images of the device arrays
+  const NetDims nd = net_dims(p, net);
+  std::vector<int8_t> lanes8(L), rank8(L, 0);
+  std::vector<int32_t> node_in_off(S.n_nodes + 1, 0), node_in(L);
+  for (int32_t i = 0; i < L; ++i) {
+    lanes8[i] = (int8_t)S.lanes[i];
+    if (!S.ring) rank8[i] = net->rank[order[i]];
+    node_in_off[S.to[i] + 1]++;
+  }
+  for (int32_t v = 0; v < S.n_nodes; ++v) node_in_off[v + 1] += node_in_off[v];
+  {
+    std::vector<int32_t> fill(node_in_off.begin(), node_in_off.end() - 1);
+    for (int32_t i = 0; i < L; ++i) node_in[fill[S.to[i]]++] = i;
+    for (int32_t v = 0; v < S.n_nodes; ++v)
+      std::sort(node_in.begin() + node_in_off[v], node_in.begin() + node_in_off[v + 1],
+                [&](int32_t a, int32_t b) { return rank8[a] < rank8[b]; });
+  }
+  std::vector<int32_t> conn_off(L + 1, 0), conn_out;
+  std::vector<int8_t> conn_lo, conn_hi;
+  if (p->flags & SIM_FLAG_TURN_LANES) {
+    for (int32_t i = 0; i < L; ++i) {
+      const int32_t e = order[i];
+      for (int64_t k = net->conn_off[e]; k < net->conn_off[e + 1]; ++k) {
+        conn_out.push_back(S.int_of[net->conn_out[k]]);
+        conn_lo.push_back(net->conn_lo[k]);
+        conn_hi.push_back(net->conn_hi[k]);
+      }
+      conn_off[i + 1] = (int32_t)conn_out.size();
+    }
+  }
+  std::vector<int32_t> lane_link(S.n_lanes), lane_base(S.n_lanes);
+  int64_t rec = 0;
+  for (int32_t i = 0; i < L; ++i) {
+    const int cap = S.len[i] * (lc_link(*p, S.lanes[i]) ? 2 : 1);
+    if (lc_link(*p, S.lanes[i]))
+      S.lc_cells = std::max(S.lc_cells, S.lanes[i] * S.len[i]);
+    for (int k = 0; k < S.lanes[i]; ++k) {
+      lane_link[S.lane0[i] + k] = i;
+      lane_base[S.lane0[i] + k] = (int32_t)rec;
+      rec += cap;
+    }
+  }
+  if (rec > INT32_MAX) return fail(c, SIM_E_CAPACITY, "too many cells");
+  S.n_records = rec;
+
+  // ---- carve and upload
+  DevScen& d = S.d;
+  Carve cv{static_cast<uint8_t*>(dev_ws), 0};
+  carve_network(cv, nd, d, S.ring);
+  if (cv.off > ws_bytes)
+    return fail(c, SIM_E_NOMEM, "workspace of %llu bytes, network needs %llu",
+                (unsigned long long)ws_bytes, (unsigned long long)cv.off);
+  S.ws = static_cast<uint8_t*>(dev_ws);
+  S.ws_bytes = ws_bytes;
+  S.ws_net = cv.off;
+  d.flags = p->flags;
+  d.vmax = p->vmax;
+  d.key0 = (uint32_t)p->seed;
+  d.key1 = (uint32_t)(p->seed >> 32);
+  d.slow_thr = p->slow_thr;
+  d.lc_thr = p->lc_thr;
+  d.lc_desp = p->lc_desp;
+  d.n_links = L;
+  d.n_lanes = S.n_lanes;
+  d.n_tiles = S.n_tiles;
+  d.lc_cells = S.lc_cells;
+  d.ring_L = S.ring ? net->len[0] : 0;
+  hipStream_t s = c->stream;
+  HIPCHK(c, up(const_cast<int32_t*>(d.link_len), S.len.data(), L, s));
+  HIPCHK(c, up(const_cast<int8_t*>(d.link_lanes), lanes8.data(), L, s));
+  HIPCHK(c, up(const_cast<int32_t*>(d.link_lane0), S.lane0.data(), L, s));
+  HIPCHK(c, up(const_cast<int32_t*>(d.link_to), S.to.data(), L, s));
+  HIPCHK(c, up(const_cast<int8_t*>(d.link_rank), rank8.data(), L, s));
+  HIPCHK(c, up(const_cast<int32_t*>(d.link_ext), S.ext_of.data(), L, s));
+  HIPCHK(c, up(const_cast<int32_t*>(d.node_in_off), node_in_off.data(), S.n_nodes + 1, s));
+  HIPCHK(c, up(const_cast<int32_t*>(d.node_in), node_in.data(), L, s));
+  HIPCHK(c, up(const_cast<int32_t*>(d.conn_off), conn_off.data(), L + 1, s));
+  HIPCHK(c, up(const_cast<int32_t*>(d.conn_out), conn_out.data(), (int64_t)conn_out.size(), s));
+  HIPCHK(c, up(const_cast<int8_t*>(d.conn_lo), conn_lo.data(), (int64_t)conn_lo.size(), s));
+  HIPCHK(c, up(const_cast<int8_t*>(d.conn_hi), conn_hi.data(), (int64_t)conn_hi.size(), s));
+  HIPCHK(c, up(const_cast<int32_t*>(d.lane_link), lane_link.data(), S.n_lanes, s));
+  HIPCHK(c, up(const_cast<int32_t*>(d.lane_base), lane_base.data(), S.n_lanes, s));
+  HIPCHK(c, up(const_cast<int2*>(d.tile_lanes), S.tiles.data(), S.n_tiles, s));
+  HIPCHK(c, hipStreamSynchronize(s));
+  S.net = true;
+  c->work_key.clear();  // slot contents changed: rebuild work lists
+  return SIM_OK;
+}
+
+extern "C" sim_status sim_load_vehicles(sim_ctx* c, int32_t slot,
+                                        const sim_vehicles* v) {
+  sim_status st = check_slot(c, slot);
+  if (st != SIM_OK) return st;
+  Slot& S = c->slots[slot];
+  if (!S.net) return fail(c, SIM_E_STATE, "slot %d has no network", slot);
+  if (!v || v->n < 0) return fail(c, SIM_E_INVAL, "bad vehicles");
+  const int32_t n = v->n;
+  const int vmax = S.p.vmax;
+  if (n > 0 && !v->depart) return fail(c, SIM_E_INVAL, "depart is NULL");
+  const bool has_init = v->init_status != nullptr;
+  if (has_init && (!v->init_lane || !v->init_x || !v->init_v ||
+                   (!S.ring && !v->init_rptr)))
+    return fail(c, SIM_E_INVAL, "incomplete initial state arrays");
+  DevScen& d = S.d;
+  hipStream_t s = c->stream;
+  // per-run device state starts empty
+  {
+    std::vector<int4> hand_a(S.n_lanes, make_int4(kTagNone, 0, 0, 0));
+    HIPCHK(c, up(d.hand_a, hand_a.data(), S.n_lanes, s));
+    HIPCHK(c, hipMemsetAsync(d.lane_hc, 0, sizeof(int2) * S.n_lanes, s));
+    HIPCHK(c, hipMemsetAsync(d.tile_ctr, 0, sizeof(long long) * C_N * S.n_tiles, s));
+    HIPCHK(c, hipMemsetAsync(d.ring_ctr, 0, sizeof(long long) * C_N, s));
+    HIPCHK(c, hipMemsetAsync(d.err, 0, sizeof(uint32_t), s));
+    HIPCHK(c, hipStreamSynchronize(s));
+  }
+
+  if (S.ring) {
+    const int32_t Lr = d.ring_L;
+    if (!has_init) return fail(c, SIM_E_INVAL, "ring mode needs initial placement");
+    if (n > kRingMax)
+      return fail(c, SIM_E_CAPACITY, "ring mode supports up to %d vehicles", kRingMax);
+    std::vector<int32_t> idx(n);
+    std::vector<uint8_t> used(Lr, 0);
+    for (int32_t i = 0; i < n; ++i) {
+      if (v->init_status[i] != 1)
+        return fail(c, SIM_E_INVAL, "ring mode: vehicle %d must start on the ring", i);
+      if (v->init_lane[i] != 0 || v->init_x[i] < 0 || v->init_x[i] >= Lr ||
+          v->init_v[i] < 0 || v->init_v[i] > vmax)
+        return fail(c, SIM_E_INVAL, "vehicle %d: placement out of range", i);
+      if (used[v->init_x[i]]++) return fail(c, SIM_E_INVAL, "two vehicles share cell %d", v->init_x[i]);
+      idx[i] = i;
+    }
+    std::sort(idx.begin(), idx.end(),
+              [&](int32_t a, int32_t b) { return v->init_x[a] < v->init_x[b]; });
+    std::vector<int32_t> rx(n), rv(n), rid(n);
+    for (int32_t j = 0; j < n; ++j) {
+      rx[j] = v->init_x[idx[j]];
+      rv[j] = v->init_v[idx[j]];
+      rid[j] = idx[j];
+    }
+    Carve cv{S.ws, S.ws_net};
+    carve_vehicles(cv, n, 0, d, true);
+    if (cv.off > S.ws_bytes)
+      return fail(c, SIM_E_NOMEM, "workspace of %llu bytes, scenario needs %llu",
+                  (unsigned long long)S.ws_bytes, (unsigned long long)cv.off);
+    d.n_veh = n;
+    d.ring_n = n;
+    d.t = v->t0;
+    HIPCHK(c, up(d.ring_x, rx.data(), n, s));
+    HIPCHK(c, up(d.ring_v, rv.data(), n, s));
+    HIPCHK(c, up(const_cast<int32_t*>(d.ring_id), rid.data(), n, s));
+    S.n_route = 0;
+    d.n_route = 0;
+  } else {
+    if (n > 0 && (!v->route_off || !v->route_links))
+      return fail(c, SIM_E_INVAL, "routes are NULL");
+    const int64_t R = n > 0 ? v->route_off[n] : 0;
+    if (n > 0 && v->route_off[0] != 0) return fail(c, SIM_E_INVAL, "route_off[0] must be 0");
+    if (R > INT32_MAX - 2) return fail(c, SIM_E_CAPACITY, "too many route entries");
+    const int32_t L = S.n_links;
+    std::vector<int32_t> rl(R);
+    for (int32_t i = 0; i < n; ++i) {
+      const int64_t a = v->route_off[i], b = v->route_off[i + 1];
+      if (b <= a) return fail(c, SIM_E_INVAL, "vehicle %d: empty route", i);
+      for (int64_t j = a; j < b; ++j) {
+        const int32_t e = v->route_links[j];
+        if (e < 0 || e >= L) return fail(c, SIM_E_INVAL, "vehicle %d: route link out of range", i);
+        rl[j] = S.int_of[e];
+        if (j > a && S.to[rl[j - 1]] != S.from[rl[j]])
+          return fail(c, SIM_E_INVAL, "vehicle %d: route links not connected", i);
+      }
+    }
+    // turn connectivity must exist for every turn a route makes
+    std::vector<int32_t> conn_off;
+    std::vector<int32_t> conn_out;
+    std::vector<int8_t> conn_lo, conn_hi;
+    const bool turn = S.p.flags & SIM_FLAG_TURN_LANES;
+    if (turn) {
+      conn_off.resize(L + 1);
+      HIPCHK(c, hipMemcpyAsync(conn_off.data(), d.conn_off, sizeof(int32_t) * (L + 1),
+                               hipMemcpyDeviceToHost, s));
+      HIPCHK(c, hipStreamSynchronize(s));
+      const int32_t C = conn_off[L];
+      conn_out.resize(C);
+      conn_lo.resize(C);
+      conn_hi.resize(C);
+      HIPCHK(c, hipMemcpyAsync(conn_out.data(), d.conn_out, sizeof(int32_t) * C, hipMemcpyDeviceToHost, s));
+      HIPCHK(c, hipMemcpyAsync(conn_lo.data(), d.conn_lo, C, hipMemcpyDeviceToHost, s));
+      HIPCHK(c, hipMemcpyAsync(conn_hi.data(), d.conn_hi, C, hipMemcpyDeviceToHost, s));
+      HIPCHK(c, hipStreamSynchronize(s));
+    }
+    auto lohi = [&](int32_t link, int32_t nxt, int& lo, int& hi) -> bool {
+      lo = 0;
+      hi = S.lanes[link] - 1;
+      if (!turn || nxt < 0) return true;
+      for (int32_t e = conn_off[link]; e < conn_off[link + 1]; ++e)
+        if (conn_out[e] == nxt) {
+          lo = conn_lo[e];
+          hi = conn_hi[e];
+          return true;
+        }
+      return false;
+    };
+    if (turn)
+      for (int32_t i = 0; i < n; ++i)
+        for (int64_t j = v->route_off[i]; j + 1 < v->route_off[i + 1]; ++j) {
+          int lo, hi;
+          if (!lohi(rl[j], rl[j + 1], lo, hi))
+            return fail(c, SIM_E_INVAL, "vehicle %d: no lane connectivity for a turn", i);
+        }
+    // initial state: active vehicles into their lanes, lead first
+    std::vector<int32_t> cnt(S.n_lanes, 0);
+    std::vector<int32_t> wait_cnt(L + 1, 0);
+    std::vector<int32_t> act;
+    for (int32_t i = 0; i < n; ++i) {
+      const int stt = has_init ? v->init_status[i] : 0;
+      if (stt == 0) {
+        wait_cnt[rl[v->route_off[i]] + 1]++;
+      } else if (stt == 1) {
+        const int32_t rp = v->init_rptr[i];
+        if (rp < 0 || v->route_off[i] + rp >= v->route_off[i + 1])
+          return fail(c, SIM_E_INVAL, "vehicle %d: rptr out of range", i);
+        const int32_t link = rl[v->route_off[i] + rp];
+        const int k = v->init_lane[i];
+        if (k < 0 || k >= S.lanes[link] || v->init_x[i] < 0 ||
+            v->init_x[i] >= S.len[link] || v->init_v[i] < 0 || v->init_v[i] > vmax)
+          return fail(c, SIM_E_INVAL, "vehicle %d: placement out of range", i);
+        cnt[S.lane0[link] + k]++;
+        act.push_back(i);
+      } else if (stt != 2) {
+        return fail(c, SIM_E_INVAL, "vehicle %d: bad status", i);
+      }
+    }
+    auto lane_of = [&](int32_t i) {
+      return S.lane0[rl[v->route_off[i] + v->init_rptr[i]]] + v->init_lane[i];
+    };
+    std::sort(act.begin(), act.end(), [&](int32_t a, int32_t b) {
+      const int32_t qa = lane_of(a), qb = lane_of(b);
+      if (qa != qb) return qa < qb;
+      return v->init_x[a] > v->init_x[b];
+    });
+    std::vector<int32_t> lane_base(S.n_lanes);
+    std::vector<int2> hc(S.n_lanes, make_int2(0, 0));
+    HIPCHK(c, hipMemcpyAsync(lane_base.data(), d.lane_base, sizeof(int32_t) * S.n_lanes,
+                             hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    // records are written sparsely: stage them and upload per lane run
+    std::vector<uint2> hot;
+    std::vector<int2> cold;
+    std::vector<int64_t> run_slot;  // first slot of each lane run
+    std::vector<int32_t> run_len, run_first;
+    for (size_t a = 0; a < act.size();) {
+      const int32_t qq = lane_of(act[a]);
+      size_t b = a;
+      while (b < act.size() && lane_of(act[b]) == qq) ++b;
+      const int32_t link = rl[v->route_off[act[a]] + v->init_rptr[act[a]]];
+      run_slot.push_back(lane_base[qq]);
+      run_len.push_back((int32_t)(b - a));
+      run_first.push_back((int32_t)hot.size());
+      for (size_t j = a; j < b; ++j) {
+        const int32_t i = act[j];
+        if (j > a && v->init_x[act[j - 1]] == v->init_x[i])
+          return fail(c, SIM_E_INVAL, "vehicles %d and %d share a cell", act[j - 1], i);
+        const int64_t rp = v->route_off[i] + v->init_rptr[i];
+        const int32_t nxt = rp + 1 < v->route_off[i + 1] ? rl[rp + 1] : -1;
+        int lo, hi;
+        lohi(link, nxt, lo, hi);
+        hot.push_back(make_uint2(pack_xvf(v->init_x[i], v->init_v[i], fl_make(nxt < 0, lo, hi)),
+                                 (uint32_t)i));
+        cold.push_back(make_int2((int32_t)rp, nxt));
+      }
+      hc[qq] = make_int2(0, (int32_t)(b - a));
+      a = b;
+    }
+    // parking queues ordered by (depart, id)
+    for (int32_t l = 0; l < L; ++l) wait_cnt[l + 1] += wait_cnt[l];
+    std::vector<int32_t> wid(wait_cnt[L]), wdep(wait_cnt[L]);
+    {
+      std::vector<int32_t> fill(wait_cnt.begin(), wait_cnt.end() - 1);
+      for (int32_t i = 0; i < n; ++i)
+        if ((has_init ? v->init_status[i] : 0) == 0) wid[fill[rl[v->route_off[i]]]++] = i;
+      for (int32_t l = 0; l < L; ++l)
+        std::sort(wid.begin() + wait_cnt[l], wid.begin() + wait_cnt[l + 1],
+                  [&](int32_t a, int32_t b) {
+                    if (v->depart[a] != v->depart[b]) return v->depart[a] < v->depart[b];
+                    return a < b;
+                  });
+      for (size_t j = 0; j < wid.size(); ++j) wdep[j] = v->depart[wid[j]];
+    }
+    std::vector<int32_t> exit_t(R, -1);
+    if (v->exit_t0) std::copy(v->exit_t0, v->exit_t0 + R, exit_t.begin());
+
+    Carve cv{S.ws, S.ws_net};
+    carve_vehicles(cv, n, R, d, false);
+    if (cv.off > S.ws_bytes)
+      return fail(c, SIM_E_NOMEM, "workspace of %llu bytes, scenario needs %llu",
+                  (unsigned long long)S.ws_bytes, (unsigned long long)cv.off);
+    d.n_veh = n;
+    d.n_route = R;
+    d.t = v->t0;
+    HIPCHK(c, up(const_cast<int32_t*>(d.wait_id), wid.data(), (int64_t)wid.size(), s));
+    HIPCHK(c, up(const_cast<int32_t*>(d.wait_dep), wdep.data(), (int64_t)wdep.size(), s));
+    HIPCHK(c, up(const_cast<int32_t*>(d.wait_off), wait_cnt.data(), L + 1, s));
+    HIPCHK(c, up(d.wait_head, wait_cnt.data(), L, s));
+    HIPCHK(c, up(const_cast<int64_t*>(d.route_off), v->route_off, n + 1, s));
+    HIPCHK(c, up(const_cast<int32_t*>(d.route_links), rl.data(), R, s));
+    HIPCHK(c, up(d.exit_t, exit_t.data(), R, s));
+    for (size_t r = 0; r < run_slot.size(); ++r) {
+      HIPCHK(c, up(d.hot + run_slot[r], hot.data() + run_first[r], run_len[r], s));
+      HIPCHK(c, up(d.cold + run_slot[r], cold.data() + run_first[r], run_len[r], s));
+    }
+    HIPCHK(c, up(d.lane_hc, hc.data(), S.n_lanes, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    S.n_route = R;
+  }
+  S.n_veh = n;
+  S.t = v->t0;
+  d.n_veh = n;
+  HIPCHK(c, hipMemcpyAsync(c->d_descs + slot, &d, sizeof(DevScen), hipMemcpyHostToDevice, s));
+  HIPCHK(c, hipStreamSynchronize(s));
+  S.veh = true;
+  c->work_key.clear();
+  return SIM_OK;
+}
+
+namespace {
+
+sim_status build_work(sim_ctx* c, const std::vector<int32_t>& net,
+                      const std::vector<int32_t>& ring) {
+  std::vector<int32_t> key(net);
+  key.push_back(-1);
+  key.insert(key.end(), ring.begin(), ring.end());
+  if (key == c->work_key) return SIM_OK;
+  // all tiles of all network slots, dealt to the 8 XCDs in contiguous chunks
+  // (workgroup w runs on XCD w mod 8)
+  std::vector<int2> all;
+  int lc = 0;
+  for (int32_t sl : net) {
+    const Slot& S = c->slots[sl];
+    for (int32_t t = 0; t < S.n_tiles; ++t) all.push_back(make_int2(sl, t));
+    lc = std::max(lc, S.lc_cells);
+  }
+  const std::vector<int2> work = xcd_interleave(all, 8);
+  if (work.size() > c->work_cap) {
+    if (c->d_work) HIPCHK(c, hipFree(c->d_work));
+    c->d_work = nullptr;
+    HIPCHK(c, hipMalloc(&c->d_work, sizeof(int2) * std::max<size_t>(work.size(), 1)));
+    c->work_cap = work.size();
+  }
+  std::vector<int32_t> list(net);
+  list.insert(list.end(), ring.begin(), ring.end());
+  if (list.size() > c->list_cap) {
+    if (c->d_list) HIPCHK(c, hipFree(c->d_list));
+    c->d_list = nullptr;
+    HIPCHK(c, hipMalloc(&c->d_list, sizeof(int) * std::max<size_t>(list.size(), 1)));
+    c->list_cap = list.size();
+  }
+  HIPCHK(c, up(c->d_work, work.data(), (int64_t)work.size(), c->stream));
+  HIPCHK(c, up(c->d_list, list.data(), (int64_t)list.size(), c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  c->n_work = (int)work.size();
+  c->n_net = (int)net.size();
+  c->n_ring = (int)ring.size();
+  c->lc_cells = lc;
+  c->work_key = key;
+  return SIM_OK;
+}
+
+// Brackets one launch with a pair of events when profiling is on.
+template <class F>
+sim_status timed(sim_ctx* c, int kind, F&& launch) {
+  if (!c->profile) {
+    HIPCHK(c, launch());
+    return SIM_OK;
+  }
+  if (c->events.size() < 2 * (c->n_pairs + 1)) {
+    for (int k = 0; k < 2; ++k) {
+      hipEvent_t e;
+      HIPCHK(c, hipEventCreate(&e));
+      c->events.push_back(e);
+    }
+    c->event_kind.push_back(0);
+  }
+  HIPCHK(c, hipEventRecord(c->events[2 * c->n_pairs], c->stream));
+  HIPCHK(c, launch());
+  HIPCHK(c, hipEventRecord(c->events[2 * c->n_pairs + 1], c->stream));
+  c->event_kind[c->n_pairs] = kind;
+  ++c->n_pairs;
+  return SIM_OK;
+}
+
+}  // namespace
+
+extern "C" sim_status sim_profile(sim_ctx* c, int32_t enable) {
+  if (!c) return SIM_E_INVAL;
+  c->profile = enable != 0;
+  return SIM_OK;
+}
+
+extern "C" sim_status sim_kernel_times(sim_ctx* c, sim_kernel_time out[3]) {
+  if (!c) return SIM_E_INVAL;
+  if (!out) return fail(c, SIM_E_INVAL, "out is NULL");
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  for (int k = 0; k < 3; ++k) out[k] = sim_kernel_time{0, 0.0};
+  for (size_t p = 0; p < c->n_pairs; ++p) {
+    float ms = 0;
+    HIPCHK(c, hipEventElapsedTime(&ms, c->events[2 * p], c->events[2 * p + 1]));
+    out[c->event_kind[p]].launches++;
+    out[c->event_kind[p]].total_ms += ms;
+  }
+  c->n_pairs = 0;
+  return SIM_OK;
+}
+
+extern "C" sim_status sim_step(sim_ctx* c, const int32_t* slots, int32_t n_slots,
+                               int32_t n_steps) {
+  if (!c) return SIM_E_INVAL;
+  if (!slots || n_slots < 1) return fail(c, SIM_E_INVAL, "no slots");
+  if (n_steps < 0) return fail(c, SIM_E_INVAL, "negative step count");
+  std::vector<int32_t> net, ring;
+  std::vector<uint8_t> seen(c->slots.size(), 0);
+  for (int32_t k = 0; k < n_slots; ++k) {
+    sim_status st = check_slot(c, slots[k]);
+    if (st != SIM_OK) return st;
+    const Slot& S = c->slots[slots[k]];
+    if (!S.net || !S.veh) return fail(c, SIM_E_STATE, "slot %d is not loaded", slots[k]);
+    if (seen[slots[k]]++) return fail(c, SIM_E_INVAL, "slot %d listed twice", slots[k]);
+    if ((int64_t)S.t + n_steps > INT32_MAX - 1)
+      return fail(c, SIM_E_CAPACITY, "step index would overflow");
+    (S.ring ? ring : net).push_back(slots[k]);
+  }
+  if (n_steps == 0) return SIM_OK;
+  sim_status st = build_work(c, net, ring);
+  if (st != SIM_OK) return st;
+  if (!net.empty()) {
+    for (int32_t s = 0; s < n_steps; ++s) {
+      st = timed(c, 0, [&] {
+        return launch_front(c->d_descs, c->d_work, c->n_work, s, c->lc_cells, c->stream);
+      });
+      if (st != SIM_OK) return st;
+      st = timed(c, 1, [&] {
+        return launch_back(c->d_descs, c->d_work, c->n_work, s, c->stream);
+      });
+      if (st != SIM_OK) return st;
+    }
+    HIPCHK(c, launch_advance(c->d_descs, c->d_list, c->n_net, n_steps, c->stream));
+  }
+  if (!ring.empty()) {
+    st = timed(c, 2, [&] {
+      return launch_ring(c->d_descs, c->d_list + c->n_net, c->n_ring, n_steps, c->stream);
+    });
+    if (st != SIM_OK) return st;
+  }
+  for (int32_t sl : net) c->slots[sl].t += n_steps;
+  for (int32_t sl : ring) c->slots[sl].t += n_steps;
+  return SIM_OK;
+}
+
+extern "C" sim_status sim_stats(sim_ctx* c, int32_t slot, sim_stats_t* out) {
+  sim_status st = check_slot(c, slot);
+  if (st != SIM_OK) return st;
+  if (!out) return fail(c, SIM_E_INVAL, "out is NULL");
+  const Slot& S = c->slots[slot];
+  if (!S.net || !S.veh) return fail(c, SIM_E_STATE, "slot %d is not loaded", slot);
+  unsigned long long h[C_N + 3];
+  uint32_t err = 0;
+  HIPCHK(c, hipMemsetAsync(c->d_stats, 0, sizeof h, c->stream));
+  HIPCHK(c, launch_stats(c->d_descs + slot, c->d_stats, S.ring ? 1 : 0, c->stream));
+  HIPCHK(c, hipMemcpyAsync(h, c->d_stats, sizeof h, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipMemcpyAsync(&err, S.d.err, sizeof err, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  std::memset(out, 0, sizeof *out);
+  out->t = S.t;
+  out->veh_updates = (int64_t)h[C_UPDATES];
+  out->sum_v = (int64_t)h[C_SUMV];
+  out->crossings = (int64_t)h[C_CROSS];
+  out->exits = (int64_t)h[C_EXITS];
+  out->lane_changes = (int64_t)h[C_LC];
+  out->insertions = (int64_t)h[C_INS];
+  out->c_occ = (int64_t)h[C_COCC];
+  out->n_active = (int64_t)h[C_N];
+  out->hash = h[C_N + 1];
+  out->n_waiting = (int64_t)h[C_N + 2];
+  out->n_arrived = S.n_veh - out->n_active - out->n_waiting;
+  out->dev_err = err;
+  if (err) return fail(c, SIM_E_DEVICE, "device error bits 0x%x", err);
+  return SIM_OK;
+}
+
+extern "C" sim_status sim_read_state(sim_ctx* c, int32_t slot, int8_t* status,
+                                     int32_t* link, int8_t* lane, int32_t* x,
+                                     int8_t* v, int32_t* rptr, int32_t* exit_t) {
+  sim_status st = check_slot(c, slot);
+  if (st != SIM_OK) return st;
+  const Slot& S = c->slots[slot];
+  if (!S.net || !S.veh) return fail(c, SIM_E_STATE, "slot %d is not loaded", slot);
+  const int64_t n = S.n_veh;
+  auto carve_out = [n](Carve& cv, ExportBufs& o) {
+    o.status = cv.take<int8_t>(n);
+    o.link = cv.take<int32_t>(n);
+    o.lane = cv.take<int8_t>(n);
+    o.x = cv.take<int32_t>(n);
+    o.v = cv.take<int8_t>(n);
+    o.rptr = cv.take<int32_t>(n);
+  };
+  ExportBufs o;
+  Carve measure{nullptr, 0};
+  carve_out(measure, o);
+  uint8_t* buf = nullptr;
+  HIPCHK(c, hipMalloc(&buf, measure.off));
+  Carve cv{buf, 0};
+  carve_out(cv, o);
+  hipError_t e = launch_export(c->d_descs + slot, o, (int)n, S.n_links, S.n_lanes,
+                               S.ring ? 1 : 0, c->stream);
+  const char* what = "export kernels";
+  auto down = [&](void* dst, const void* src, size_t b, const char* name) {
+    if (e == hipSuccess && dst && b) {
+      e = hipMemcpyAsync(dst, src, b, hipMemcpyDeviceToHost, c->stream);
+      what = name;
+    }
+  };
+  down(status, o.status, n, "copy status");
+  down(link, o.link, 4 * n, "copy link");
+  down(lane, o.lane, n, "copy lane");
+  down(x, o.x, 4 * n, "copy x");
+  down(v, o.v, n, "copy v");
+  down(rptr, o.rptr, 4 * n, "copy rptr");
+  if (!S.ring) down(exit_t, S.d.exit_t, 4 * (size_t)S.n_route, "copy exit_t");
+  if (e == hipSuccess) {
+    e = hipStreamSynchronize(c->stream);
+    what = "synchronize";
+  }
+  (void)hipFree(buf);
+  if (e != hipSuccess)
+    return fail(c, SIM_E_DEVICE, "read_state: %s: %s", what, hipGetErrorString(e));
+  return SIM_OK;
+}
+
+extern "C" sim_status sim_link_costs(sim_ctx* c, int32_t slot, float* out) {
+  sim_status st = check_slot(c, slot);
+  if (st != SIM_OK) return st;
+  const Slot& S = c->slots[slot];
+  if (!S.net) return fail(c, SIM_E_STATE, "slot %d has no network", slot);
+  if (!out) return fail(c, SIM_E_INVAL, "out is NULL");
+  std::vector<long long> ctr((size_t)S.n_tiles * C_N);
+  HIPCHK(c, hipMemcpyAsync(ctr.data(), S.d.tile_ctr, sizeof(long long) * ctr.size(),
+                           hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  for (int32_t t = 0; t < S.n_tiles; ++t) {
+    const int2 tl = S.tiles[t];
+    double cells = 0;
+    std::vector<int32_t> links;
+    for (int32_t q = tl.x; q < tl.x + tl.y; ++q) {
+      // lanes of one link are contiguous; collect each link once
+      int32_t lk = (int32_t)(std::upper_bound(S.lane0.begin(), S.lane0.end(), q) -
+                             S.lane0.begin()) - 1;
+      if (links.empty() || links.back() != lk) links.push_back(lk);
+    }
+    for (int32_t lk : links) cells += (double)S.len[lk] * S.lanes[lk];
+    const double cyc = (double)ctr[(size_t)t * C_N + C_CYCLES];
+    for (int32_t lk : links)
+      out[S.ext_of[lk]] = (float)(cells > 0 ? cyc * S.len[lk] * S.lanes[lk] / cells : 0);
+  }
+  return SIM_OK;
+}
+
+extern "C" sim_status sim_tiling_info(const sim_ctx* cc, int32_t slot, sim_tiling* out) {
+  sim_ctx* c = const_cast<sim_ctx*>(cc);
+  sim_status st = check_slot(c, slot);
+  if (st != SIM_OK) return st;
+  if (!out) return fail(c, SIM_E_INVAL, "out is NULL");
+  const Slot& S = c->slots[slot];
+  if (!S.net) return fail(c, SIM_E_STATE, "slot %d has no network", slot);
+  *out = S.tiling;
+  return SIM_OK;
+}
+
+extern "C" sim_status sim_unload(sim_ctx* c, int32_t slot) {
+  sim_status st = check_slot(c, slot);
+  if (st != SIM_OK) return st;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  c->slots[slot] = Slot();
+  c->work_key.clear();
+  return SIM_OK;
+}

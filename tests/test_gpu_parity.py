@@ -1,0 +1,150 @@
+"""GPU parity: libtransims (through its C ABI) against the CPU oracle, bit
+for bit, on the same seeded inputs.  Every step is integer, so the bar is
+exact equality of every vehicle's state, every exit time and every counter."""
+import dataclasses
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_cs_0105004_amd import scenarios as S
+
+from hand_cases import build, check, load_cases
+from parity import assert_same_state, assert_same_stats, run_side_by_side
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def sim():
+    from paper_cs_0105004_amd.sim import Context
+    ctx = Context(max_slots=8)
+    yield ctx
+    ctx.close()
+
+
+def test_c1_ring_full_run(sim):
+    scen = S.ring()  # 1000 cells, 150 vehicles, vmax 5, p 0.2, seed 42
+    run_side_by_side(sim, 0, scen, 1000, every=100, full_at=(1, 2, 10))
+
+
+@pytest.mark.parametrize("p,vmax", [("0", 5), ("1", 5), ("0.5", 1),
+                                    ("0.2", 7)])
+def test_ring_variants(sim, p, vmax):
+    scen = S.ring(1000, 150, vmax, p=p, seed=42)
+    run_side_by_side(sim, 0, scen, 300, every=50)
+
+
+def test_ring_edge_cases(sim):
+    cases = [S.ring(1, 1, 5, "0.3", seed=3), S.ring(7, 0, 5, "0.3"),
+             S.ring(5, 5, 3, "0.3"), S.ring(9, 1, 7, "0.5", seed=9),
+             S.ring(4096, 4096, 5, "0.2"), S.ring(20000, 4096, 5, "0.2"),
+             S.ring(300, 299, 2, "0.1", seed=77)]
+    for scen in cases:
+        print("case", scen.link_len[0], scen.n_veh, scen.vmax, flush=True)
+        run_side_by_side(sim, 1, scen, 40, every=10)
+
+
+def test_many_rings_in_one_launch(sim):
+    scens = [S.ring(int(L), int(n), 5, "0.25", seed=100 + k, placement_seed=k)
+             for k, (L, n) in enumerate([(50, 10), (1000, 150), (333, 300),
+                                         (2, 1), (700, 0), (4000, 1000)])]
+    for k, sc in enumerate(scens):
+        sim.load(k, sc)
+    sim.step(list(range(len(scens))), 123)
+    for k, sc in enumerate(scens):
+        o = oracle.OracleSim(sc)
+        o.step(123)
+        assert_same_stats(sim.stats(k), o.stats(), f"ring {k}")
+        assert_same_state(sim.state(k), o.state(), f"ring {k}")
+
+
+@pytest.mark.parametrize("case", load_cases(), ids=lambda c: c["name"])
+def test_hand_worked_cases(sim, case):
+    scen = build(case)
+    sim.load(0, scen)
+    sim.step(0, case["steps"])
+    check(case, sim.state(0), sim.stats(0))
+
+
+@pytest.mark.parametrize("p", ["0", "0.2"])
+def test_loop_of_links(sim, p):
+    scen = S.loop_of_links([12, 30, 9, 41, 6], 40, vmax=5, p=p, seed=5, T=200)
+    run_side_by_side(sim, 0, scen, 200, every=1, full_at=(1, 50))
+
+
+def small_grid(flags=0, scale=0.01, depart_max=150, seed=2024):
+    scen = S.portland_like(scale=scale, T=400, depart_max=depart_max,
+                           seed=seed, flags=flags)
+    if flags & S.FLAG_TURN_LANES:
+        scen.conn_off, scen.conn_out, scen.conn_lo, scen.conn_hi = \
+            S._ranks_and_conn(scen.n_nodes, scen.link_from, scen.link_to,
+                              scen.link_lanes, scen.node_xy, True)[1:]
+    return scen
+
+
+def test_small_grid_every_step(sim):
+    run_side_by_side(sim, 0, small_grid(), 400, every=1,
+                     full_at=(1, 2, 3, 50, 100, 200, 300))
+
+
+@pytest.mark.parametrize("flags", [S.FLAG_LANE_CHANGE,
+                                   S.FLAG_LANE_CHANGE | S.FLAG_TURN_LANES])
+def test_small_grid_lane_change(sim, flags):
+    scen = small_grid(flags)
+    orc = run_side_by_side(sim, 0, scen, 400, every=1,
+                           full_at=(1, 2, 50, 150, 300))
+    assert orc.stats()["lane_changes"] > 0
+
+
+def test_lane_change_slowdown_draws(sim):
+    scen = small_grid(S.FLAG_LANE_CHANGE | S.FLAG_TURN_LANES)
+    scen.lc_thr = S.prob_threshold("0.6")
+    run_side_by_side(sim, 0, scen, 300, every=25)
+
+
+@pytest.mark.parametrize("tile_lanes", [1, 4, 37, 64])
+def test_tile_size_does_not_change_results(tile_lanes):
+    from paper_cs_0105004_amd.sim import Context
+    ctx = Context(max_slots=1, tile_lanes=tile_lanes)
+    try:
+        run_side_by_side(ctx, 0, small_grid(S.FLAG_LANE_CHANGE, seed=7), 250,
+                         every=50)
+    finally:
+        ctx.close()
+
+
+def test_medium_grid_ragged_tiles(sim):
+    scen = S.portland_like(scale=0.06, T=500, depart_max=400, seed=11)
+    run_side_by_side(sim, 0, scen, 500, every=100, full_at=(250,))
+
+
+def test_batched_slots_equal_solo(sim):
+    scens = [small_grid(seed=31), small_grid(S.FLAG_LANE_CHANGE, seed=32),
+             S.loop_of_links([12, 30, 9], 20, p="0.3", seed=3, T=300),
+             S.ring(500, 80, 5, "0.2", seed=33)]
+    for k, sc in enumerate(scens):
+        sim.load(k, sc)
+    sim.step(list(range(len(scens))), 150)
+    sim.step([1, 3], 50)  # uneven progress
+    steps = [150, 200, 150, 200]
+    for k, sc in enumerate(scens):
+        o = oracle.OracleSim(sc)
+        o.step(steps[k])
+        assert_same_stats(sim.stats(k), o.stats(), f"slot {k}")
+        assert_same_state(sim.state(k), o.state(), f"slot {k}")
+
+
+def test_restart_from_saved_state(sim):
+    scen = small_grid(S.FLAG_LANE_CHANGE | S.FLAG_TURN_LANES, seed=41)
+    sim.load(0, scen)
+    sim.step(0, 170)
+    mid = sim.state(0)
+    sim.step(0, 100)
+    end = sim.state(0)
+    sim.load(1, scen.with_state(mid, 170))
+    sim.step(1, 100)
+    assert_same_state(sim.state(1), end, "restart")
+    o = oracle.OracleSim(scen)
+    o.step(270)
+    assert_same_state(end, o.state(), "restart vs oracle")
