@@ -72,7 +72,13 @@ typedef struct {
   int32_t abi_version; /* must be SIM_ABI_VERSION                           */
   int32_t max_slots;   /* number of independent scenario slots (>= 1)       */
   void* stream;        /* hipStream_t for all device work; NULL = default   */
-  int32_t tile_lanes;  /* lanes per workgroup tile, 1..64; 0 = default (16) */
+  int32_t tile_lanes;   /* lanes per workgroup tile (whole links), 1..64;
+                           0 = default (16)                                 */
+  int32_t back_pieces;  /* wavefronts per tile in the move sub-step, which
+                           share the tile's lanes by vehicle load, 1..8;
+                           0 = default (4)                                  */
+  int32_t graph_steps;  /* steps per HIP graph replay in sim_step; 0 =
+                           default (64); < 0 = launch kernels one by one    */
   int32_t reserved;
 } sim_config;
 

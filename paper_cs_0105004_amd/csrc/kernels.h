@@ -7,15 +7,27 @@
 
 namespace tr {
 
-// One step of every tile in `work` ({slot, tile} pairs, in dispatch order):
+// One step of every tile in `work` ({slot, first lane, lanes, tile}, in
+// dispatch order; slot >= 0: every item belongs to that slot):
 // the front kernel merges arrivals, lets vehicles leave parking, runs the
 // lane-change sub-step and publishes per-lane summaries; the back kernel
 // resolves the intersections and moves every vehicle (second sub-step).
 // lc_cells: largest lanes*len over links that change lanes (LDS lattice).
-hipError_t launch_front(const DevScen* d_descs, const int2* d_work, int n_work,
-                        int step, int lc_cells, hipStream_t s);
-hipError_t launch_back(const DevScen* d_descs, const int2* d_work, int n_work,
-                       int step, hipStream_t s);
+// pieces: most move wavefronts per tile (single slot; 1 = one per tile)
+hipError_t launch_front(const DevScen* d_descs, int slot, const int4* d_work,
+                        int n_work, int pieces, int step, int lc_cells,
+                        hipStream_t s);
+// The move kernel: one wavefront per work item plus, for a single slot,
+// n_extra wavefronts for the runs of heavy tiles the front kernel listed.
+hipError_t launch_back(const DevScen* d_descs, int slot, const int4* d_work,
+                       int n_work, int n_extra, int step, hipStream_t s);
+// Host stubs of the step kernels, for building HIP graphs:
+//   front(descs, slot, work, pieces, step), back(descs, slot, work, n_work,
+//   step), advance(descs, slots, n, k)
+void* front_kernel(bool batched);
+void* back_kernel(bool batched);
+void* advance_kernel();
+constexpr int kFrontThreads = kWave, kBackThreadsPerPiece = kWave;
 // descs[slots[i]].t += k for i < n
 hipError_t launch_advance(DevScen* d_descs, const int* d_slots, int n, int k,
                           hipStream_t s);

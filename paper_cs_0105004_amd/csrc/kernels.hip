@@ -20,13 +20,35 @@
 //            slot of its target lane (at most one per lane and step).
 #include "kernels.h"
 #include "philox.h"
-#include "../../include/transims.h"
+#include "transims.h"
 
 namespace tr {
 
 namespace {
 
 constexpr int kRingBlock = 256;
+// load of a lane in the move sub-step: its vehicles plus a fixed cost; a
+// tile gets one move wavefront per kPieceCost of load (up to a limit)
+constexpr int kLaneCost = 4;
+constexpr int kPieceCost = 256;
+
+// Pointers read from a descriptor are generic; casting them to the global
+// address space lets the compiler use global (not flat) memory instructions,
+// whose completion is tracked apart from LDS traffic.
+// HIP's vector classes cannot be copied out of that address space, so the
+// kernels use the compiler's own vector types there.
+#define GAS __attribute__((address_space(1)))
+typedef int v2i __attribute__((ext_vector_type(2)));
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef unsigned v2u __attribute__((ext_vector_type(2)));
+template <class T>
+__device__ __forceinline__ GAS T* gp(T* p) {
+  return (GAS T*)p;
+}
+template <class V, class T>
+__device__ __forceinline__ GAS V* gpv(T* p) {
+  return (GAS V*)(void*)p;
+}
 
 __device__ __forceinline__ int wrapi(int a, int cap) {
   return a >= cap ? a - cap : a;
@@ -39,20 +61,6 @@ __device__ __forceinline__ int hp_par(int hp) { return hp >> 16; }
 // record slot of the j-th vehicle (0 = lead) of a lane
 __device__ __forceinline__ int rec_slot(int base, int hp, int len, int j) {
   return base + hp_par(hp) * len + wrapi(hp_head(hp) + j, len);
-}
-
-// flags of a vehicle entering `link` whose next route link is nxt (-1: none)
-__device__ uint32_t route_flags(const DevScen& S, int link, int nxt) {
-  int lo = 0, hi = S.link_lanes[link] - 1;
-  if (nxt >= 0 && (S.flags & SIM_FLAG_TURN_LANES)) {
-    for (int e = S.conn_off[link]; e < S.conn_off[link + 1]; ++e)
-      if (S.conn_out[e] == nxt) {
-        lo = S.conn_lo[e];
-        hi = S.conn_hi[e];
-        break;
-      }
-  }
-  return fl_make(nxt < 0, lo, hi);
 }
 
 __device__ __forceinline__ unsigned long long wave_sum(unsigned long long v) {
@@ -123,25 +131,24 @@ __device__ int lc_decide(const DevScen& S, const short* lat, int len,
 // Runs the lane-change sub-step on every multi-lane link of the tile.  The
 // link's lanes are staged in LDS as a lattice of record offsets; movers are
 // applied at once and, when any vehicle moved, the lanes' queues are
-// rebuilt in the other half of their double buffer.
-__device__ int lane_change_tile(const DevScen& S, int t, int2 tl, int* s_hp,
-                                int* s_cnt, short* lat, signed char* dec) {
+// rebuilt in the other half of their double buffer.  s_info/s_hp/s_cnt hold
+// the tile's lanes.
+__device__ int lane_change_tile(const DevScen& S, int t, int nl,
+                                const int4* s_info, int* s_hp, int* s_cnt,
+                                short* lat, signed char* dec) {
   const int i = threadIdx.x;
   int moves_total = 0;
-  const int first_link = S.lane_link[tl.x];
-  const int last_link = S.lane_link[tl.x + tl.y - 1];
-  for (int link = first_link; link <= last_link; ++link) {
-    const int lanes = S.link_lanes[link];
-    if (lanes < 2) continue;
-    const int lane0 = S.link_lane0[link];
-    const int tb = lane0 - tl.x;
+  for (int tb = 0; tb < nl; ++tb) {
+    const uint32_t meta = (uint32_t)s_info[tb].y;
+    const int lanes = lmeta_lanes(meta);
+    if (lmeta_k(meta) != 0 || lanes < 2) continue;
     int pre[5];
     pre[0] = 0;
     for (int k = 0; k < lanes; ++k) pre[k + 1] = pre[k] + s_cnt[tb + k];
     const int total = pre[lanes];
     if (total == 0) continue;
-    const int len = S.link_len[link];
-    const int region = S.lane_base[lane0];
+    const int len = lmeta_len(meta);
+    const int region = s_info[tb].x;  // lanes' double buffers are contiguous
     const int cells = lanes * len;
     for (int c = i; c < cells; c += kWave) {
       lat[c] = -1;
@@ -151,16 +158,14 @@ __device__ int lane_change_tile(const DevScen& S, int t, int2 tl, int* s_hp,
     for (int f = i; f < total; f += kWave) {
       int k = 0;
       while (f >= pre[k + 1]) ++k;
-      const int slot = rec_slot(S.lane_base[lane0 + k], s_hp[tb + k], len,
-                                f - pre[k]);
+      const int slot = rec_slot(s_info[tb + k].x, s_hp[tb + k], len, f - pre[k]);
       lat[k * len + xvf_x(S.hot[slot].x)] = (short)(slot - region);
     }
     __syncthreads();
     for (int f = i; f < total; f += kWave) {
       int k = 0;
       while (f >= pre[k + 1]) ++k;
-      const int slot = rec_slot(S.lane_base[lane0 + k], s_hp[tb + k], len,
-                                f - pre[k]);
+      const int slot = rec_slot(s_info[tb + k].x, s_hp[tb + k], len, f - pre[k]);
       const uint2 hw = S.hot[slot];
       const int x = xvf_x(hw.x);
       const int d = lc_decide(S, lat, len, lanes, k, x, xvf_v(hw.x),
@@ -192,7 +197,7 @@ __device__ int lane_change_tile(const DevScen& S, int t, int2 tl, int* s_hp,
     if (moved > 0) {
       const int npar = 1 - hp_par(s_hp[tb]);
       for (int k = 0; k < lanes; ++k) {
-        const int dst0 = S.lane_base[lane0 + k] + npar * len;
+        const int dst0 = s_info[tb + k].x + npar * len;
         int n = 0;
         for (int c0 = 0; c0 < len; c0 += kWave) {
           const int x = len - 1 - (c0 + i);
@@ -220,80 +225,115 @@ __device__ int lane_change_tile(const DevScen& S, int t, int2 tl, int* s_hp,
 }  // namespace
 
 // ---------------------------------------------------------------------------
+// Work items are {slot, first lane, lanes, tile}.  With kBatched false every
+// item belongs to slot `slot`, whose descriptor is then read without waiting
+// for the work item.
 
+template <bool kBatched>
 __global__ __launch_bounds__(kWave) void k_front(
-    const DevScen* __restrict__ descs, const int2* __restrict__ work,
-    int step) {
+    const DevScen* __restrict__ descs, int slot, const int4* __restrict__ work,
+    int pieces, int step) {
   extern __shared__ unsigned char dyn[];
+  __shared__ int4 s_info[kMaxTileLanes];
   __shared__ int s_hp[kMaxTileLanes], s_cnt[kMaxTileLanes];
   const long long c0 = wall_clock64();
-  const int2 w = work[blockIdx.x];
-  const DevScen& S = descs[w.x];
+  const int4 w = work[blockIdx.x];
+  const DevScen& S = descs[kBatched ? w.x : slot];
   const int t = S.t + step;
-  const int2 tl = S.tile_lanes[w.y];
+  const int vmax = S.vmax;
+  const GAS v4i* __restrict__ lane_info = gpv<v4i>(S.lane_info);
+  GAS v2i* __restrict__ lane_hc = gpv<v2i>(S.lane_hc);
+  GAS v4i* __restrict__ lane_sum = gpv<v4i>(S.lane_sum);
+  const GAS v4i* __restrict__ lane_ends = gpv<v4i>(S.lane_ends);
+  GAS int32_t* __restrict__ claim_a = gp(S.claim);
+  const GAS v4i* __restrict__ hand_a = gpv<v4i>(S.hand_a);
+  const GAS int32_t* __restrict__ hand_b = gp(S.hand_b);
+  // the lane-change pass reaches the records through the descriptor too
+  GAS v2u* hot = gpv<v2u>(S.hot);
+  GAS v2i* cold = gpv<v2i>(S.cold);
+  const GAS int32_t* __restrict__ wait_off = gp(S.wait_off);
+  const GAS v4i* __restrict__ wait_rec = gpv<v4i>(S.wait_rec);
+  const GAS int32_t* __restrict__ wait_info0 = gp(S.wait_info0);
+  GAS int32_t* __restrict__ wait_head = gp(S.wait_head);
   const int i = threadIdx.x;
-  const bool act = i < tl.y;
-  const int gid = tl.x + i;
+  const int nl = w.z;
+  const bool act = i < nl;
+  const int gid = w.y + i;
 
-  int hp = 0, cnt = 0, link = 0, k = 0, len = 1, base = 0, lanes = 1,
-      lane0 = 0;
-  uint32_t rear_w = 0;
+  v4i info = {0, 0, 0, 0};
+  int hp = 0, cnt = 0, len = 1, k = 0, lanes = 1;
+  uint32_t rear_w = 0, lead_w = 0;
+  int lead_ninfo = 0;
   bool empty0 = false;
   if (act) {
-    const int2 hc = S.lane_hc[gid];
+    info = lane_info[gid];
+    const v2i hc = lane_hc[gid];
+    const v4i ends = lane_ends[gid];
+    const v4i ha = hand_a[gid];
+    const int hb = hand_b[gid];
     hp = hc.x;
     cnt = hc.y;
-    link = S.lane_link[gid];
-    lane0 = S.link_lane0[link];
-    k = gid - lane0;
-    len = S.link_len[link];
-    base = S.lane_base[gid];
-    lanes = S.link_lanes[link];
+    const uint32_t meta = (uint32_t)info.y;
+    len = lmeta_len(meta);
+    k = lmeta_k(meta);
+    lanes = lmeta_lanes(meta);
+    const int base = info.x;
+    // the lane's two end records as the move left them
+    lead_w = (uint32_t)ends.x;
+    lead_ninfo = ends.y;
+    rear_w = (uint32_t)ends.z;
     // the vehicle the upstream node handed over in the previous step
-    const int4 ha = S.hand_a[gid];
     if (ha.x == t - 1) {
       if (cnt >= len) {
         atomicOr(S.err, SIM_DEVERR_LANE_FULL);
       } else {
         const int slot = rec_slot(base, hp, len, cnt);
-        S.hot[slot] = make_uint2((uint32_t)ha.y, (uint32_t)ha.z);
-        S.cold[slot] = make_int2(ha.w, S.hand_nxt[gid]);
+        hot[slot] = (v2u){(uint32_t)ha.y, (uint32_t)ha.z};
+        cold[slot] = (v2i){ha.w, hb};
+        rear_w = (uint32_t)ha.y;
+        if (cnt == 0) {
+          lead_w = rear_w;
+          lead_ninfo = hb;
+        }
         ++cnt;
       }
     }
-    empty0 = true;
-    if (cnt > 0) {
-      rear_w = S.hot[rec_slot(base, hp, len, cnt - 1)].x;
-      empty0 = xvf_x(rear_w) != 0;
-    }
+    empty0 = cnt == 0 || xvf_x(rear_w) != 0;
   }
   // parking: the lowest lane of the link whose cell 0 is empty takes the
   // head of the link's queue if it has departed
   const unsigned long long free0 = __ballot(act && empty0);
   int ins = 0;
   if (act && empty0) {
-    const unsigned long long lm =
-        (free0 >> (lane0 - tl.x)) & ((1ull << lanes) - 1ull);
+    const unsigned long long lm = (free0 >> (i - k)) & ((1ull << lanes) - 1ull);
     if (__builtin_ctzll(lm) == k) {
-      const int h = S.wait_head[link];
-      if (h < S.wait_off[link + 1] && S.wait_dep[h] <= t) {
-        const int id = S.wait_id[h];
-        S.wait_head[link] = h + 1;
-        const long long rp = S.route_off[id];
-        const int nxt =
-            rp + 1 < S.route_off[id + 1] ? S.route_links[rp + 1] : -1;
-        rear_w = pack_xvf(0, 0, route_flags(S, link, nxt));
-        const int slot = rec_slot(base, hp, len, cnt);
-        S.hot[slot] = make_uint2(rear_w, (uint32_t)id);
-        S.cold[slot] = make_int2((int)rp, nxt);
-        ++cnt;
-        ins = 1;
+      const int link = info.z;
+      const int h = wait_head[link];
+      const int hend = wait_off[link + 1];
+      const int hq = h < hend ? h : 0;  // a valid index either way
+      const v4i wr = wait_rec[hq];
+      const uint32_t info0 = (uint32_t)wait_info0[hq];
+      if (h < hend && wr.y <= t) {
+        {
+          wait_head[link] = h + 1;
+          rear_w = pack_xvf(0, 0, rinfo_flags(info0));
+          const int slot = rec_slot(info.x, hp, len, cnt);
+          hot[slot] = (v2u){rear_w, (uint32_t)wr.x};
+          cold[slot] = (v2i){wr.z, wr.w};
+          if (cnt == 0) {
+            lead_w = rear_w;
+            lead_ninfo = wr.w;
+          }
+          ++cnt;
+          ins = 1;
+        }
       }
     }
   }
   int lc_moves = 0;
   if (S.flags & SIM_FLAG_LANE_CHANGE) {
     if (act) {
+      s_info[i] = make_int4(info.x, info.y, info.z, info.w);
       s_hp[i] = hp;
       s_cnt[i] = cnt;
     }
@@ -301,185 +341,314 @@ __global__ __launch_bounds__(kWave) void k_front(
     short* lat = reinterpret_cast<short*>(dyn);
     signed char* dec =
         reinterpret_cast<signed char*>(dyn) + (size_t)2 * S.lc_cells;
-    lc_moves = lane_change_tile(S, t, tl, s_hp, s_cnt, lat, dec);
+    lc_moves = lane_change_tile(S, t, nl, s_info, s_hp, s_cnt, lat, dec);
     __syncthreads();
-    if (act) {
+    if (act && lc_moves > 0 && hp != s_hp[i]) {
       hp = s_hp[i];
       cnt = s_cnt[i];
-      if (cnt > 0) rear_w = S.hot[rec_slot(base, hp, len, cnt - 1)].x;
+      if (cnt > 0) {
+        const int ls = rec_slot(info.x, hp, len, 0);
+        lead_w = hot[ls].x;
+        lead_ninfo = cold[ls].y;
+        rear_w = hot[rec_slot(info.x, hp, len, cnt - 1)].x;
+      }
     }
   }
   if (act) {
-    int tgt = -1, rear_x = len;
-    if (cnt > 0) {
-      rear_x = xvf_x(rear_w);
-      const int ls = rec_slot(base, hp, len, 0);
-      const uint32_t lw = S.hot[ls].x;
-      if (len - 1 - xvf_x(lw) < S.vmax) {
-        if (xvf_fl(lw) & kFlLast) {
-          tgt = -2;
-        } else {
-          const int nxt = S.cold[ls].y;
-          tgt = S.link_lane0[nxt] + min(k, (int)S.link_lanes[nxt] - 1);
-        }
+    int tgt = -1;
+    const int rear_x = cnt > 0 ? xvf_x(rear_w) : len;
+    if (cnt > 0 && len - 1 - xvf_x(lead_w) < vmax) {
+      if (xvf_fl(lead_w) & kFlLast) {
+        tgt = -2;  // the trip ends at this node
+      } else {
+        const uint32_t ni = (uint32_t)lead_ninfo;
+        tgt = rinfo_lane0(ni) + min(k, rinfo_lanes(ni) - 1);
+        // priority among the candidates aiming at one lane: smallest
+        // (rank of the link, lane); they all enter the same node
+        atomicMin((int*)&claim_a[tgt], lmeta_rank((uint32_t)info.y) * 8 + k);
       }
     }
-    S.lane_sum[gid] = make_int2(tgt, rear_x);
-    S.lane_hc[gid] = make_int2(hp, cnt);
+    lane_sum[gid] = (v4i){tgt, rear_x, hp, cnt};
+    lane_hc[gid] = (v2i){hp, cnt};
+  }
+  // runs of this tile for the move sub-step: a tile heavier than
+  // kPieceCost gets more wavefronts, listed for the move kernel
+  if (pieces > 1 && S.xcap > 0) {
+    const unsigned long long T =
+        wave_sum((unsigned long long)(act ? cnt + kLaneCost : 0));
+    const int np = min(pieces, (int)((T + kPieceCost - 1) / kPieceCost));
+    if (i == 0) {
+      int got = 0;
+      if (np > 1) {
+        const int base = atomicAdd(&S.xcount[t & 1], np - 1);
+        got = max(0, min(S.xcap - base, np - 1));
+        for (int r = 0; r < got; ++r)
+          S.xlist[base + r] =
+              make_int4(w.y, w.z | ((r + 1) << 8) | ((got + 1) << 16), w.w, 0);
+      }
+      S.tile_np[w.w] = got + 1;
+    }
   }
   const unsigned long long n_ins = wave_sum((unsigned long long)ins);
   if (i == 0) {
-    long long* ctr = S.tile_ctr + (long long)w.y * C_N;
-    ctr[C_INS] += (long long)n_ins;
-    ctr[C_LC] += lc_moves;
-    ctr[C_CYCLES] += wall_clock64() - c0;
+    long long* ctr = S.ftile_ctr + (long long)w.w * C_N;
+    if (n_ins) atomicAdd((unsigned long long*)&ctr[C_INS], n_ins);
+    if (lc_moves) atomicAdd((unsigned long long*)&ctr[C_LC],
+                            (unsigned long long)lc_moves);
+    atomicAdd((unsigned long long*)&ctr[C_CYCLES],
+              (unsigned long long)(wall_clock64() - c0));
   }
 }
 
+// Orders this lane's LDS accesses before the next ones of any lane of the
+// wavefront: a wavefront executes its LDS instructions in order, so keeping
+// the compiler from moving them is enough, and nothing waits on memory.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// The back kernel: one wavefront per tile of at most 64 lanes, plus the
+// extra wavefronts the front kernel listed for heavy tiles.  The wavefronts
+// of a tile cut it into as many contiguous runs of lanes of about equal load
+// (vehicles + kLaneCost per lane) -- the paper's load balancing by measured
+// load, redone every step from the current counts -- and each takes one run.
+// Lane threads resolve the intersections, then the vehicles of the run are
+// updated 64 at a time.
+constexpr int kGroup = 2;  // chunks of 64 vehicles loaded before updating
+
+template <bool kBatched>
 __global__ __launch_bounds__(kWave) void k_back(
-    const DevScen* __restrict__ descs, const int2* __restrict__ work,
-    int step) {
+    const DevScen* __restrict__ descs, int slot, const int4* __restrict__ work,
+    int n_work, int step) {
   __shared__ int s_pre[kMaxTileLanes + 1];
   __shared__ int s_base[kMaxTileLanes], s_hp[kMaxTileLanes],
-      s_len[kMaxTileLanes], s_extra[kMaxTileLanes], s_tgt[kMaxTileLanes],
+      s_len[kMaxTileLanes], s_key[kMaxTileLanes], s_tgt[kMaxTileLanes],
       s_left[kMaxTileLanes];
+  __shared__ int4 s_ends[kMaxTileLanes];    // new lead xvf/ninfo, rear xvf
+  __shared__ int2 s_second[kMaxTileLanes];  // the vehicle behind the lead
   const long long c0 = wall_clock64();
-  const int2 w = work[blockIdx.x];
-  const DevScen& S = descs[w.x];
+  // the next step's list of extra wavefronts starts empty (done before any
+  // wavefront can leave early)
+  if (!kBatched && blockIdx.x == 0 && threadIdx.x == 0 && descs[slot].xcap > 0)
+    descs[slot].xcount[(descs[slot].t + step + 1) & 1] = 0;
+  int4 w;
+  int piece = 0, np = 1;
+  if ((int)blockIdx.x < n_work) {
+    w = work[blockIdx.x];
+    if (!kBatched && descs[slot].xcap > 0) np = descs[slot].tile_np[w.w];
+  } else {  // an extra wavefront of a heavy tile (single slot only)
+    const DevScen& S1 = descs[slot];
+    const int e = (int)blockIdx.x - n_work;
+    const int t1 = S1.t + step;
+    if (e >= min(S1.xcount[t1 & 1], S1.xcap)) return;
+    const int4 x = S1.xlist[e];
+    w = make_int4(slot, x.x, x.y & 0xFF, x.z);
+    piece = (x.y >> 8) & 0xFF;
+    np = x.y >> 16;
+  }
+  const DevScen& S = descs[kBatched ? w.x : slot];
+  // everything the kernel touches, in registers, as global pointers
   const int t = S.t + step;
   const int vmax = S.vmax;
-  const int2 tl = S.tile_lanes[w.y];
-  const int nl = tl.y;
+  const uint32_t key0 = S.key0, key1 = S.key1;
+  const uint64_t slow_thr = S.slow_thr;
+  const GAS v4i* __restrict__ lane_info = gpv<v4i>(S.lane_info);
+  GAS v2i* __restrict__ lane_hc = gpv<v2i>(S.lane_hc);
+  const GAS v4i* __restrict__ lane_sum = gpv<v4i>(S.lane_sum);
+  GAS v4i* __restrict__ lane_ends = gpv<v4i>(S.lane_ends);
+  GAS int32_t* __restrict__ claim_a = gp(S.claim);
+  GAS v4i* __restrict__ hand_a = gpv<v4i>(S.hand_a);
+  GAS int32_t* __restrict__ hand_b = gp(S.hand_b);
+  // hot and hot_w name the same records (loads / xvf stores): no restrict
+  GAS v2u* hot = gpv<v2u>(S.hot);
+  GAS uint32_t* hot_w = gpv<uint32_t>(S.hot);  // word 0 of a record = xvf
+  const GAS v2i* __restrict__ cold = gpv<v2i>(S.cold);
+  const GAS uint32_t* __restrict__ route_info = gp(S.route_info);
+  GAS int32_t* __restrict__ exit_t = gp(S.exit_t);
+  // counters of a run live at the entry of its first lane (set below)
+  GAS unsigned long long* __restrict__ ctr = nullptr;
+  const int nl = w.z;
   const int i = threadIdx.x;
-  const bool act = i < nl;
-  const int gid = tl.x + i;
+  const int gid = w.y + i;
 
-  int cnt = 0, len = 1, hp = 0;
-  if (act) {
-    const int2 hc = S.lane_hc[gid];
-    hp = hc.x;
-    cnt = hc.y;
-    const int link = S.lane_link[gid];
-    const int k = gid - S.link_lane0[link];
-    len = S.link_len[link];
-    const int2 sum = S.lane_sum[gid];
-    int extra = 0;
-    if (sum.x == -2) {
-      extra = vmax;  // the trip ends at this node
-    } else if (sum.x >= 0) {
-      // priority: the candidate with the smallest (rank, lane) aiming at the
-      // same target lane wins; in-links are sorted by rank
-      const int node = S.link_to[link];
-      const int mykey = S.link_rank[link] * 8 + k;
-      bool win = true;
-      for (int e = S.node_in_off[node]; e < S.node_in_off[node + 1] && win;
-           ++e) {
-        const int l2 = S.node_in[e];
-        const int r2 = S.link_rank[l2] * 8;
-        if (r2 > mykey) break;
-        const int b2 = S.link_lane0[l2];
-        const int n2 = S.link_lanes[l2];
-        for (int k2 = 0; k2 < n2 && r2 + k2 < mykey; ++k2)
-          if (S.lane_sum[b2 + k2].x == sum.x) {
-            win = false;
-            break;
-          }
-      }
-      if (win) extra = min(vmax, S.lane_sum[sum.x].y);
+  // The lane counts come from the summary the front kernel published: the
+  // other wavefronts of this tile rewrite lane_hc of their own lanes while
+  // this one may still be reading, so the split must not depend on it.
+  int cnt = 0;
+  v4i sum = {-1, 0, 0, 0};
+  v4i info = {0, 0, 0, 0};
+  if (i < nl) {
+    sum = lane_sum[gid];
+    info = lane_info[gid];
+  }
+  // this wavefront's run of lanes
+  bool act = false;
+  {
+    const int cost = i < nl ? sum.w + kLaneCost : 0;
+    int ci = cost;
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+      const int y = __shfl_up(ci, off);
+      if (i >= off) ci += y;
     }
-    s_base[i] = S.lane_base[gid];
+    const int T = __builtin_amdgcn_readfirstlane(__shfl(ci, kWave - 1));
+    const int id = (int)(((long long)(ci - cost) * np) / T);
+    act = i < nl && id == piece;
+    if (__ballot(act) == 0ull) return;  // no run for this wavefront
+  }
+  int len = 1, hp = 0;
+  if (act) {
+    hp = sum.z;
+    cnt = sum.w;
+    const uint32_t meta = (uint32_t)info.y;
+    len = lmeta_len(meta);
+    s_base[i] = info.x;
     s_hp[i] = hp;
     s_len[i] = len;
-    s_extra[i] = extra;
     s_tgt[i] = sum.x;
+    s_key[i] = lmeta_rank(meta) * 8 + lmeta_k(meta);
     s_left[i] = 0;
+    s_ends[i] = make_int4(0, 0, 0, 0);
   }
-  // exclusive prefix of the lane counts
+  // exclusive prefix of the run's lane counts (zero outside the run)
   int incl = cnt;
 #pragma unroll
   for (int off = 1; off < kWave; off <<= 1) {
     const int y = __shfl_up(incl, off);
     if (i >= off) incl += y;
   }
-  const int total = __shfl(incl, kWave - 1);
-  if (act) s_pre[i] = incl - cnt;
+  // uniform across the wavefront: keep it in a scalar register
+  const int total = __builtin_amdgcn_readfirstlane(__shfl(incl, kWave - 1));
+  // every lane of the tile gets its entry (lanes outside the run hold no
+  // vehicles of it), so the search below only ever lands on the run's lanes
+  if (i < nl) s_pre[i] = incl - cnt;
   if (i == 0) s_pre[nl] = total;
   const unsigned long long cocc =
       wave_sum((unsigned long long)(cnt > 0 ? len : 0));
-  __syncthreads();
+  wave_lds_sync();
 
   unsigned long long sumv = 0, cross = 0, exits = 0;
-  // chunks from the rear so that every vehicle reads the position of the one
-  // ahead before that one is rewritten
-  for (int f0 = total > 0 ? ((total - 1) / kWave) * kWave : -1; f0 >= 0;
-       f0 -= kWave) {
-    const int f = f0 + i;
-    if (f < total) {
-      int lo = 0, hi = nl;
-      while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (s_pre[mid] <= f) lo = mid;
-        else hi = mid;
+  const int nchunk = (total + kWave - 1) / kWave;
+  // Groups of chunks run from the rear: a group loads every record it needs
+  // before rewriting any, so each vehicle reads the position of the one
+  // ahead before it changes.
+  for (int g0 = ((nchunk - 1) / kGroup) * kGroup; nchunk > 0 && g0 >= 0;
+       g0 -= kGroup) {
+    v2u hw[kGroup];
+    v2i cw[kGroup];
+    uint32_t ahead[kGroup];
+    int sl[kGroup], lij[kGroup], clm[kGroup], rear[kGroup];
+    {
+      // Every thread loads (threads past the last vehicle repeat it), so no
+      // load sits in a divergent branch and all of them stay in flight.
+#pragma unroll
+      for (int c = 0; c < kGroup; ++c) {
+        const int fr = (g0 + c) * kWave + i;
+        const int f = min(fr, total - 1);
+        int lo = 0, hi = nl;
+        while (hi - lo > 1) {
+          const int mid = (lo + hi) >> 1;
+          if (s_pre[mid] <= f) lo = mid;
+          else hi = mid;
+        }
+        const int j = f - s_pre[lo];
+        const int llen = s_len[lo], lbase = s_base[lo], lhp = s_hp[lo];
+        sl[c] = rec_slot(lbase, lhp, llen, j);
+        // vehicles that need no neighbour / route state read their own
+        // record or their lane's lead instead
+        const int sa = j > 0 ? rec_slot(lbase, lhp, llen, j - 1) : sl[c];
+        const int sc = j <= 1 ? sl[c] : rec_slot(lbase, lhp, llen, 0);
+        // the lead of a lane near its node also fetches the claim on its
+        // target lane and that lane's rearmost position
+        const int tg = s_tgt[lo];
+        const int q = (j == 0 && tg >= 0) ? tg : w.y + lo;
+        hw[c] = hot[sl[c]];
+        ahead[c] = hot_w[2 * sa];
+        cw[c] = cold[sc];
+        clm[c] = claim_a[q];
+        rear[c] = lane_sum[q].y;
+        lij[c] = fr < total ? (lo | (j << 8)) : -1;
       }
-      const int li = lo;
-      const int j = f - s_pre[li];
-      const int llen = s_len[li], lbase = s_base[li], lhp = s_hp[li];
-      const int slot = rec_slot(lbase, lhp, llen, j);
-      const uint2 hw = S.hot[slot];
-      const int x = xvf_x(hw.x), v = xvf_v(hw.x);
-      const uint32_t fl = xvf_fl(hw.x);
-      int gap;
-      if (j > 0) {
-        gap = xvf_x(S.hot[rec_slot(lbase, lhp, llen, j - 1)].x) - x - 1;
-      } else {
-        gap = llen - 1 - x + s_extra[li];
+    }
+#pragma unroll
+    for (int c = 0; c < kGroup; ++c) {
+      if (lij[c] < 0) continue;
+      const int li = lij[c] & 0xFF, j = lij[c] >> 8;
+      const int llen = s_len[li];
+      const int x = xvf_x(hw[c].x), v = xvf_v(hw[c].x);
+      const uint32_t fl = xvf_fl(hw[c].x);
+      int extra = 0;  // cells the lead may drive past the link end
+      if (j == 0) {
+        const int tg = s_tgt[li];
+        if (tg == -2) {
+          extra = vmax;  // the trip ends at this node
+        } else if (tg >= 0 && clm[c] == s_key[li]) {
+          extra = min(vmax, rear[c]);  // priority among the candidates
+          claim_a[tg] = INT32_MAX;     // the winner clears the claim
+        }
       }
+      const int gap = j > 0 ? xvf_x(ahead[c]) - x - 1 : llen - 1 - x + extra;
       const int v1 = min(v + 1, vmax);
       const int v2 = min(v1, gap);
-      const uint32_t u = veh_draw(hw.y, (uint32_t)t, 1u, S.key0, S.key1);
-      const int v3 = (v2 > 0 && (uint64_t)u < S.slow_thr) ? v2 - 1 : v2;
+      const uint32_t u = veh_draw(hw[c].y, (uint32_t)t, 1u, key0, key1);
+      const int v3 = (v2 > 0 && (uint64_t)u < slow_thr) ? v2 - 1 : v2;
       const int nx = x + v3;
       sumv += v3;
       if (nx < llen) {
-        S.hot[slot].x = pack_xvf(nx, v3, fl);
+        const uint32_t nw = pack_xvf(nx, v3, fl);
+        hot_w[2 * sl[c]] = nw;
+        const int lcnt = s_pre[li + 1] - s_pre[li];
+        if (j == 0) {
+          s_ends[li].x = (int)nw;
+          s_ends[li].y = cw[c].y;
+        } else if (j == 1) {
+          s_second[li] = make_int2((int)nw, cw[c].y);
+        }
+        if (j == lcnt - 1) s_ends[li].z = (int)nw;
       } else {  // only the lead vehicle can pass the node
-        const int2 cw = S.cold[slot];
-        S.exit_t[cw.x] = t;
+        const int rp = cw[c].x;
+        exit_t[rp] = t;
         s_left[li] = 1;
         if (fl & kFlLast) {
           ++exits;
         } else {
-          const int id = (int)hw.y;
-          const int nl2 = cw.y;
-          const int nn = (long long)cw.x + 2 < S.route_off[id + 1]
-                             ? S.route_links[cw.x + 2]
-                             : -1;
-          const int tgt = s_tgt[li];
-          S.hand_nxt[tgt] = nn;
-          S.hand_a[tgt] = make_int4(
-              t, (int)pack_xvf(nx - llen, v3, route_flags(S, nl2, nn)), id,
-              cw.x + 1);
+          const uint32_t nfl = rinfo_flags((uint32_t)cw[c].y);
+          const int tg = s_tgt[li];
+          hand_b[tg] = (nfl & kFlLast) ? 0 : (int)route_info[rp + 2];
+          hand_a[tg] = (v4i){t, (int)pack_xvf(nx - llen, v3, nfl),
+                             (int)hw[c].y, rp + 1};
           ++cross;
         }
       }
     }
   }
-  __syncthreads();
-  if (act && s_left[i]) {
-    const int h = wrapi(hp_head(hp) + 1, len);
-    S.lane_hc[gid] = make_int2((hp & ~0xFFFF) | h, cnt - 1);
+  wave_lds_sync();
+  if (act) {
+    int4 e = s_ends[i];
+    if (s_left[i]) {
+      const int h = wrapi(hp_head(hp) + 1, len);
+      lane_hc[gid] = (v2i){(hp & ~0xFFFF) | h, cnt - 1};
+      const int2 sec = s_second[i];
+      e.x = sec.x;  // the vehicle behind is the new lead
+      e.y = sec.y;
+    }
+    lane_ends[gid] = (v4i){e.x, e.y, e.z, e.w};
   }
   sumv = wave_sum(sumv);
   cross = wave_sum(cross);
   exits = wave_sum(exits);
+  const int first = __builtin_amdgcn_readfirstlane(
+      __builtin_ctzll(__ballot(act)));  // the run's first lane in the tile
+  ctr = (GAS unsigned long long*)gp(S.tile_ctr + (long long)(w.y + first) * C_N);
   if (i == 0) {
-    long long* ctr = S.tile_ctr + (long long)w.y * C_N;
-    ctr[C_UPDATES] += total;
-    ctr[C_SUMV] += (long long)sumv;
-    ctr[C_CROSS] += (long long)cross;
-    ctr[C_EXITS] += (long long)exits;
-    ctr[C_COCC] += (long long)cocc;
-    ctr[C_CYCLES] += wall_clock64() - c0;
+    atomicAdd((unsigned long long*)&ctr[C_UPDATES], (unsigned long long)total);
+    atomicAdd((unsigned long long*)&ctr[C_SUMV], sumv);
+    if (cross) atomicAdd((unsigned long long*)&ctr[C_CROSS], cross);
+    if (exits) atomicAdd((unsigned long long*)&ctr[C_EXITS], exits);
+    atomicAdd((unsigned long long*)&ctr[C_COCC], cocc);
+    atomicAdd((unsigned long long*)&ctr[C_CYCLES],
+              (unsigned long long)(wall_clock64() - c0));
   }
 }
 
@@ -588,15 +757,16 @@ __global__ void k_stats(const DevScen* d, unsigned long long* out, int ring) {
         atomicAdd(&out[c], (unsigned long long)S.ring_ctr[c]);
     }
   } else {
+    // move-tile counters: one per lane at most (balanced tiles included)
     const long long n1 = S.n_veh, n2 = n1 + S.n_links, n3 = n2 + S.n_lanes,
-                    n4 = n3 + S.n_tiles;
-    for (long long g = g0; g < n4; g += stride) {
+                    n4 = n3 + S.n_lanes, n5 = n4 + S.n_ftiles;
+    for (long long g = g0; g < n5; g += stride) {
       if (g < n1) {
         h += veh_hash((int)g, kArrived, 0, 0, 0, 0, 0);
       } else if (g < n2) {
         const int link = (int)(g - n1);
         for (int q = S.wait_head[link]; q < S.wait_off[link + 1]; ++q) {
-          const int id = S.wait_id[q];
+          const int id = S.wait_rec[q].x;
           h += veh_hash(id, kWaiting, 0, 0, 0, 0, 0) -
                veh_hash(id, kArrived, 0, 0, 0, 0, 0);
           ++wait;
@@ -604,10 +774,11 @@ __global__ void k_stats(const DevScen* d, unsigned long long* out, int ring) {
       } else if (g < n3) {
         const int gid = (int)(g - n2);
         const int2 hc = S.lane_hc[gid];
-        const int link = S.lane_link[gid];
-        const int k = gid - S.link_lane0[link];
-        const int len = S.link_len[link];
-        const int base = S.lane_base[gid];
+        const int4 info = S.lane_info[gid];
+        const int link = info.z;
+        const int k = lmeta_k((uint32_t)info.y);
+        const int len = lmeta_len((uint32_t)info.y);
+        const int base = info.x;
         for (int j = 0; j < hc.y; ++j) {
           const int slot = rec_slot(base, hc.x, len, j);
           const uint2 hw = S.hot[slot];
@@ -627,10 +798,14 @@ __global__ void k_stats(const DevScen* d, unsigned long long* out, int ring) {
                veh_hash(id, kArrived, 0, 0, 0, 0, 0);
           ++act;
         }
-      } else {
+      } else if (g < n4) {
         const long long tile = g - n3;
         for (int c = 0; c < C_N; ++c)
           atomicAdd(&out[c], (unsigned long long)S.tile_ctr[tile * C_N + c]);
+      } else {
+        const long long tile = g - n4;
+        for (int c = 0; c < C_N; ++c)
+          atomicAdd(&out[c], (unsigned long long)S.ftile_ctr[tile * C_N + c]);
       }
     }
   }
@@ -664,14 +839,15 @@ __global__ void k_export_set(const DevScen* d, ExportBufs o, int ring) {
   }
   if (g < S.n_links) {
     for (int q = S.wait_head[g]; q < S.wait_off[g + 1]; ++q)
-      o.status[S.wait_id[q]] = kWaiting;
+      o.status[S.wait_rec[q].x] = kWaiting;
   } else if (g < S.n_links + S.n_lanes) {
     const int gid = g - S.n_links;
     const int2 hc = S.lane_hc[gid];
-    const int link = S.lane_link[gid];
-    const int k = gid - S.link_lane0[link];
-    const int len = S.link_len[link];
-    const int base = S.lane_base[gid];
+    const int4 info = S.lane_info[gid];
+    const int link = info.z;
+    const int k = lmeta_k((uint32_t)info.y);
+    const int len = lmeta_len((uint32_t)info.y);
+    const int base = info.x;
     for (int j = 0; j < hc.y; ++j) {
       const int slot = rec_slot(base, hc.x, len, j);
       const uint2 hw = S.hot[slot];
@@ -698,26 +874,46 @@ __global__ void k_export_set(const DevScen* d, ExportBufs o, int ring) {
 
 // ---- launchers -------------------------------------------------------------
 
+hipError_t launch_front(const DevScen* d_descs, int slot, const int4* d_work,
+                        int n_work, int pieces, int step, int lc_cells,
+                        hipStream_t s) {
+  if (n_work <= 0) return hipSuccess;
+  (void)hipGetLastError();
+  if (slot < 0)
+    hipLaunchKernelGGL(k_front<true>, dim3(n_work), dim3(kWave),
+                       (size_t)3 * lc_cells, s, d_descs, 0, d_work, 1, step);
+  else
+    hipLaunchKernelGGL(k_front<false>, dim3(n_work), dim3(kWave),
+                       (size_t)3 * lc_cells, s, d_descs, slot, d_work, pieces,
+                       step);
+  return hipGetLastError();
+}
+
+hipError_t launch_back(const DevScen* d_descs, int slot, const int4* d_work,
+                       int n_work, int n_extra, int step, hipStream_t s) {
+  if (n_work <= 0) return hipSuccess;
+  (void)hipGetLastError();
+  if (slot < 0)
+    hipLaunchKernelGGL(k_back<true>, dim3(n_work), dim3(kWave), 0, s, d_descs,
+                       0, d_work, n_work, step);
+  else
+    hipLaunchKernelGGL(k_back<false>, dim3(n_work + n_extra), dim3(kWave), 0,
+                       s, d_descs, slot, d_work, n_work, step);
+  return hipGetLastError();
+}
+
+void* front_kernel(bool batched) {
+  return batched ? reinterpret_cast<void*>(&k_front<true>)
+                 : reinterpret_cast<void*>(&k_front<false>);
+}
+void* back_kernel(bool batched) {
+  return batched ? reinterpret_cast<void*>(&k_back<true>)
+                 : reinterpret_cast<void*>(&k_back<false>);
+}
+void* advance_kernel() { return reinterpret_cast<void*>(&k_advance); }
+
 // Each launcher first clears any error left by earlier runtime calls of this
 // thread, so that the status it returns is the launch's own.
-hipError_t launch_front(const DevScen* d_descs, const int2* d_work, int n_work,
-                        int step, int lc_cells, hipStream_t s) {
-  if (n_work <= 0) return hipSuccess;
-  (void)hipGetLastError();
-  hipLaunchKernelGGL(k_front, dim3(n_work), dim3(kWave), (size_t)3 * lc_cells,
-                     s, d_descs, d_work, step);
-  return hipGetLastError();
-}
-
-hipError_t launch_back(const DevScen* d_descs, const int2* d_work, int n_work,
-                       int step, hipStream_t s) {
-  if (n_work <= 0) return hipSuccess;
-  (void)hipGetLastError();
-  hipLaunchKernelGGL(k_back, dim3(n_work), dim3(kWave), 0, s, d_descs, d_work,
-                     step);
-  return hipGetLastError();
-}
-
 hipError_t launch_advance(DevScen* d_descs, const int* d_slots, int n, int k,
                           hipStream_t s) {
   if (n <= 0) return hipSuccess;

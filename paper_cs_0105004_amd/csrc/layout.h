@@ -6,10 +6,17 @@
 // inside a lane, so the order only changes when a vehicle enters at the rear
 // (parking, arrival from an upstream node, lane change) or leaves at the
 // front (next link, trip end) -- or moves sideways.  A record is
-//   hot  = { xvf, id }   8 bytes, read and its xvf word rewritten every step
-//   cold = { rp, nxt }   8 bytes, read only when the vehicle is near a node
+//   hot  = { xvf, id }     8 bytes, read and its xvf word rewritten every step
+//   cold = { rp, ninfo }   8 bytes, read only when the vehicle nears a node
 // xvf packs x (bits 0-15), v (bits 16-19) and flags (bits 20-24: last link;
-// lowest and highest lane from which the next turn is made).
+// lowest and highest lane from which the next turn is made).  rp is the
+// vehicle's absolute route index; ninfo is the route info word of the next
+// route entry (see below), so the lane it aims at needs no further lookup.
+//
+// Route info word (one per route entry r, replacing the link id):
+//   bits 0-23 first lane id of link route[r]; 24-25 lanes-1;
+//   26-27 / 28-29 lowest / highest lane of route[r] from which the turn into
+//   route[r+1] is made; 30 r is the last entry of the route.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -32,6 +39,39 @@ __host__ __device__ inline int xvf_v(uint32_t w) {
 __host__ __device__ inline uint32_t xvf_fl(uint32_t w) { return w >> 20; }
 
 constexpr uint32_t kFlLast = 1u;
+
+__host__ __device__ inline uint32_t rinfo_make(int lane0, int lanes, int lo,
+                                               int hi, bool last) {
+  return (uint32_t)lane0 | ((uint32_t)(lanes - 1) << 24) |
+         ((uint32_t)lo << 26) | ((uint32_t)hi << 28) |
+         (last ? (1u << 30) : 0u);
+}
+__host__ __device__ inline int rinfo_lane0(uint32_t r) {
+  return (int)(r & 0xFFFFFFu);
+}
+__host__ __device__ inline int rinfo_lanes(uint32_t r) {
+  return (int)((r >> 24) & 3u) + 1;
+}
+// record flags of a vehicle on the link of route entry with info r
+__host__ __device__ inline uint32_t rinfo_flags(uint32_t r) {
+  return ((r >> 30) & 1u) | (((r >> 26) & 3u) << 1) | (((r >> 28) & 3u) << 3);
+}
+
+// static per-lane word: len (bits 0-14), lane index k (15-16), lanes-1
+// (17-18), rank of the link at its downstream node (19-25)
+__host__ __device__ inline uint32_t lmeta_make(int len, int k, int lanes,
+                                               int rank) {
+  return (uint32_t)len | ((uint32_t)k << 15) | ((uint32_t)(lanes - 1) << 17) |
+         ((uint32_t)rank << 19);
+}
+__host__ __device__ inline int lmeta_len(uint32_t m) { return (int)(m & 0x7FFFu); }
+__host__ __device__ inline int lmeta_k(uint32_t m) { return (int)((m >> 15) & 3u); }
+__host__ __device__ inline int lmeta_lanes(uint32_t m) {
+  return (int)((m >> 17) & 3u) + 1;
+}
+__host__ __device__ inline int lmeta_rank(uint32_t m) {
+  return (int)((m >> 19) & 0x7Fu);
+}
 __host__ __device__ inline uint32_t fl_make(bool last, int lo, int hi) {
   return (last ? kFlLast : 0u) | ((uint32_t)lo << 1) | ((uint32_t)hi << 3);
 }
@@ -51,9 +91,11 @@ enum : int {
   C_N
 };
 
-// lane summary written by the front kernel for the back kernel
+// lane summary written by the front kernel for the back kernel, which never
+// modifies it:
 //   x = target lane id of the lead vehicle (-1: not near the node, -2: trip
-//       ends at the node), y = x of the rearmost vehicle (len if empty)
+//       ends at the node), y = x of the rearmost vehicle (len if empty),
+//   z = head|parity and w = count of the lane's queue as the move finds it
 
 struct DevScen {
   uint32_t flags;
@@ -63,45 +105,44 @@ struct DevScen {
   uint64_t lc_thr;
   int32_t lc_desp;
   int32_t t;  // index of the next step
-  int32_t n_links, n_lanes, n_tiles, n_veh;
+  int32_t n_links, n_lanes, n_tiles, n_ftiles, n_veh;
   int32_t ring_L, ring_n;
   int32_t lc_cells;  // largest lanes*len of a link that changes lanes
-  int32_t pad0;
   int64_t n_route;
   // links, in the library's internal (tile) order
-  const int32_t* link_len;
-  const int8_t* link_lanes;
-  const int32_t* link_lane0;  // lane id of lane 0
-  const int32_t* link_to;
-  const int8_t* link_rank;
   const int32_t* link_ext;    // caller's link id
-  const int32_t* node_in_off; // in-links of a node, sorted by rank
-  const int32_t* node_in;
-  const int32_t* conn_off;
-  const int32_t* conn_out;
-  const int8_t* conn_lo;
-  const int8_t* conn_hi;
-  // lanes
-  const int32_t* lane_link;
-  const int32_t* lane_base;  // first record slot of the lane's ring buffer
-  int2* lane_hc;             // {head, count}
-  int2* lane_sum;            // see above
+  // lanes: {record base, lmeta, link, lane id of the link's lane 0}
+  const int4* lane_info;
+  int2* lane_hc;             // {head | parity << 16, count}
+  int4* lane_ends;           // after the move: {lead xvf, lead ninfo, rear xvf}
+  int4* lane_sum;            // {target, rear x, head|parity, count}
+  int32_t* claim;            // smallest (rank, lane) key aiming at the lane
   int4* hand_a;              // arrival handoff {tag = t, xvf, id, rp}
-  int32_t* hand_nxt;         // arrival handoff: next link
+  int32_t* hand_b;           // arrival handoff: ninfo
   // vehicle records
   uint2* hot;
   int2* cold;
-  // tiles
-  const int2* tile_lanes;  // {first lane, lanes}
-  long long* tile_ctr;     // [n_tiles * C_N]
-  // parking queues per link, ordered by (depart, id)
+  // tiles: the front kernel works on small tiles (one wavefront), the back
+  // kernel on large ones (several wavefronts share the vehicles)
+  long long* tile_ctr;     // [n_lanes * C_N], move runs (by first lane)
+  long long* ftile_ctr;    // [n_ftiles * C_N], front tiles
+  // Heavy tiles get extra move wavefronts: the front kernel decides each
+  // tile's number of runs (tile_np) and lists the runs beyond the first in
+  // xlist {first lane, lanes | run << 8 | runs << 16, tile, 0}; xcount[t & 1]
+  // counts them (reset one step ahead by the move kernel).
+  int32_t* tile_np;
+  int4* xlist;
+  int32_t* xcount;
+  int32_t xcap;  // entries of xlist (0: every tile is one run)
+  // parking queues per link, ordered by (depart, id):
+  // wait_rec = {id, depart, rp of the first entry, ninfo of the second}
   const int32_t* wait_off;
-  const int32_t* wait_id;
-  const int32_t* wait_dep;
+  const int4* wait_rec;
+  const int32_t* wait_info0;  // route info of the first entry
   int32_t* wait_head;
-  // routes (internal link ids)
+  // routes
   const int64_t* route_off;
-  const int32_t* route_links;
+  const uint32_t* route_info;
   int32_t* exit_t;
   // ring mode (vehicles in cyclic order)
   int32_t* ring_x;

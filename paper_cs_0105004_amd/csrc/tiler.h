@@ -16,7 +16,7 @@
 #include <cstdint>
 #include <vector>
 
-#include "../../include/transims.h"
+#include "transims.h"
 
 namespace tr {
 

@@ -1,6 +1,6 @@
 // transims.cpp -- host side of libtransims: input checks, link tiling,
 // device layout, launches.  See include/transims.h for the contract.
-#include "../../include/transims.h"
+#include "transims.h"
 
 #include <hip/hip_runtime.h>
 
@@ -23,15 +23,19 @@ namespace {
 
 constexpr int kLcMaxLen = 2048;  // longest multi-lane link that changes lanes
 constexpr int kDefaultTileLanes = 16;
+constexpr int kDefaultBackPieces = 4;
+constexpr int kDefaultGraphSteps = 64;
 
 struct Slot {
   bool net = false, veh = false, ring = false;
   sim_params p{};
-  int32_t n_nodes = 0, n_links = 0, n_lanes = 0, n_tiles = 0, n_veh = 0;
+  int32_t n_nodes = 0, n_links = 0, n_lanes = 0, n_tiles = 0, n_ftiles = 0, n_veh = 0;
   int64_t n_route = 0, n_records = 0, n_cells = 0;
   std::vector<int32_t> ext_of, int_of;  // internal <-> caller link ids
-  std::vector<int32_t> len, lanes, lane0, from, to;  // internal order
-  std::vector<int2> tiles;
+  std::vector<int32_t> len, lanes, lane0, from, to, base;  // internal order
+  std::vector<int32_t> conn_off, conn_out;  // internal ids (turn lanes)
+  std::vector<int8_t> conn_lo, conn_hi;
+  std::vector<int2> tiles, ftiles;  // move sub-step / lane-change sub-step
   std::vector<double> weight;  // internal order
   uint8_t* ws = nullptr;
   uint64_t ws_bytes = 0, ws_net = 0;
@@ -49,13 +53,18 @@ struct sim_ctx {
   int device = 0;
   std::vector<Slot> slots;
   DevScen* d_descs = nullptr;
-  int2* d_work = nullptr;
+  int4* d_work = nullptr;
   size_t work_cap = 0;
   int* d_list = nullptr;  // network slots, then ring slots
   size_t list_cap = 0;
   unsigned long long* d_stats = nullptr;
   std::vector<int32_t> work_key;
   int n_work = 0, n_net = 0, n_ring = 0, lc_cells = 0;
+  int single_slot = -1;  // the only network slot of the work list, or -1
+  int n_extra = 0;       // extra move wavefronts of the single slot
+  // a HIP graph of graph_steps steps of the current work list
+  hipGraphExec_t graph = nullptr;
+  int graph_k = 0;
   // kernel timing
   bool profile = false;
   std::vector<hipEvent_t> events;  // pairs around launches
@@ -102,34 +111,34 @@ bool lc_link(const sim_params& p, int lanes) {
 }
 
 struct NetDims {
-  int64_t L, Q, rec, nodes, conn;
+  int64_t L, Q, rec, nodes, conn, xcap;
 };
+
+constexpr int64_t kExtraRunsMax = 1024;  // extra move wavefronts per step
+
+// entries of the list of extra move wavefronts for `tiles` tiles
+int64_t extra_cap(int64_t tiles, int pieces) {
+  return std::min<int64_t>(tiles * std::max(pieces - 1, 0), kExtraRunsMax);
+}
 
 // device arrays of the network part; pointers are null when measuring
 void carve_network(Carve& cv, const NetDims& nd, DevScen& d, bool ring) {
   const int64_t L = nd.L, Q = nd.Q;
-  d.link_len = cv.take<int32_t>(L);
-  d.link_lanes = cv.take<int8_t>(L);
-  d.link_lane0 = cv.take<int32_t>(L);
-  d.link_to = cv.take<int32_t>(L);
-  d.link_rank = cv.take<int8_t>(L);
   d.link_ext = cv.take<int32_t>(L);
-  d.node_in_off = cv.take<int32_t>(nd.nodes + 1);
-  d.node_in = cv.take<int32_t>(L);
-  d.conn_off = cv.take<int32_t>(L + 1);
-  d.conn_out = cv.take<int32_t>(nd.conn);
-  d.conn_lo = cv.take<int8_t>(nd.conn);
-  d.conn_hi = cv.take<int8_t>(nd.conn);
-  d.lane_link = cv.take<int32_t>(Q);
-  d.lane_base = cv.take<int32_t>(Q);
+  d.lane_info = cv.take<int4>(Q);
   d.lane_hc = cv.take<int2>(Q);
-  d.lane_sum = cv.take<int2>(Q);
+  d.lane_sum = cv.take<int4>(Q);
+  d.claim = cv.take<int32_t>(Q);
   d.hand_a = cv.take<int4>(Q);
-  d.hand_nxt = cv.take<int32_t>(Q);
+  d.hand_b = cv.take<int32_t>(Q);
   d.hot = cv.take<uint2>(ring ? 0 : nd.rec);
   d.cold = cv.take<int2>(ring ? 0 : nd.rec);
-  d.tile_lanes = cv.take<int2>(Q);  // at most one tile per lane
-  d.tile_ctr = cv.take<long long>(Q * C_N);
+  d.lane_ends = cv.take<int4>(Q);
+  d.tile_ctr = cv.take<long long>(Q * C_N);  // at most one tile per lane
+  d.ftile_ctr = cv.take<long long>(Q * C_N);
+  d.tile_np = cv.take<int32_t>(Q);  // at most one tile per lane
+  d.xlist = cv.take<int4>(nd.xcap);
+  d.xcount = cv.take<int32_t>(2);
   d.wait_off = cv.take<int32_t>(L + 1);
   d.wait_head = cv.take<int32_t>(L);
   d.ring_ctr = cv.take<long long>(C_N);
@@ -137,10 +146,10 @@ void carve_network(Carve& cv, const NetDims& nd, DevScen& d, bool ring) {
 }
 
 void carve_vehicles(Carve& cv, int64_t n, int64_t R, DevScen& d, bool ring) {
-  d.wait_id = cv.take<int32_t>(ring ? 0 : n);
-  d.wait_dep = cv.take<int32_t>(ring ? 0 : n);
+  d.wait_rec = cv.take<int4>(ring ? 0 : n);
+  d.wait_info0 = cv.take<int32_t>(ring ? 0 : n);
   d.route_off = cv.take<int64_t>(ring ? 0 : n + 1);
-  d.route_links = cv.take<int32_t>(R);
+  d.route_info = cv.take<uint32_t>(R);
   d.exit_t = cv.take<int32_t>(R);
   d.ring_x = cv.take<int32_t>(ring ? n : 0);
   d.ring_v = cv.take<int32_t>(ring ? n : 0);
@@ -217,13 +226,14 @@ sim_status check_network(sim_ctx* c, const sim_params* p, const sim_network* n) 
   return SIM_OK;
 }
 
-NetDims net_dims(const sim_params* p, const sim_network* n) {
-  NetDims nd{n->n_links, 0, 0, std::max(n->n_nodes, 1), 0};
+NetDims net_dims(const sim_params* p, const sim_network* n, int pieces) {
+  NetDims nd{n->n_links, 0, 0, std::max(n->n_nodes, 1), 0, 0};
   for (int32_t l = 0; l < n->n_links; ++l) {
     nd.Q += n->lanes[l];
     nd.rec += (int64_t)n->lanes[l] * n->len[l] * (lc_link(*p, n->lanes[l]) ? 2 : 1);
   }
   if ((p->flags & SIM_FLAG_TURN_LANES) && n->conn_off) nd.conn = n->conn_off[n->n_links];
+  nd.xcap = extra_cap(nd.Q, pieces);  // tiles <= lanes
   return nd;
 }
 
@@ -250,10 +260,13 @@ extern "C" sim_status sim_create(const sim_config* cfg, sim_ctx** out) {
   if (cfg->abi_version != SIM_ABI_VERSION) return SIM_E_ABI;
   if (cfg->max_slots < 1 || cfg->max_slots > 65536) return SIM_E_INVAL;
   if (cfg->tile_lanes < 0 || cfg->tile_lanes > kMaxTileLanes) return SIM_E_INVAL;
+  if (cfg->back_pieces < 0 || cfg->back_pieces > 8) return SIM_E_INVAL;
   sim_ctx* c = new (std::nothrow) sim_ctx();
   if (!c) return SIM_E_CAPACITY;
   c->cfg = *cfg;
   if (c->cfg.tile_lanes == 0) c->cfg.tile_lanes = kDefaultTileLanes;
+  if (c->cfg.back_pieces == 0) c->cfg.back_pieces = kDefaultBackPieces;
+  if (c->cfg.graph_steps == 0) c->cfg.graph_steps = kDefaultGraphSteps;
   c->stream = reinterpret_cast<hipStream_t>(cfg->stream);
   c->slots.resize(cfg->max_slots);
   if (hipGetDevice(&c->device) != hipSuccess ||
@@ -275,6 +288,7 @@ extern "C" sim_status sim_destroy(sim_ctx* c) {
   if (c->d_stats) (void)hipFree(c->d_stats);
   if (c->d_work) (void)hipFree(c->d_work);
   if (c->d_list) (void)hipFree(c->d_list);
+  if (c->graph) (void)hipGraphExecDestroy(c->graph);
   delete c;
   return SIM_OK;
 }
@@ -294,7 +308,7 @@ extern "C" sim_status sim_footprint(const sim_ctx* cc, const sim_params* p,
   const bool ring = p->flags & SIM_FLAG_RING;
   DevScen d{};
   Carve cv{nullptr, 0};
-  carve_network(cv, net_dims(p, net), d, ring);
+  carve_network(cv, net_dims(p, net, c ? c->cfg.back_pieces : kDefaultBackPieces), d, ring);
   if (veh) {
     if (veh->n < 0) return fail(c, SIM_E_INVAL, "negative vehicle count");
     const int64_t R = (!ring && veh->route_off) ? veh->route_off[veh->n] : 0;
@@ -359,55 +373,46 @@ extern "C" sim_status sim_load_network(sim_ctx* c, int32_t slot,
     S.n_cells += (int64_t)S.len[i] * S.lanes[i];
   }
   S.n_lanes = q;
-  S.tiles = pack_tiles(S.lanes, c->cfg.tile_lanes);
-  S.n_tiles = (int32_t)S.tiles.size();
+  S.ftiles = pack_tiles(S.lanes, c->cfg.tile_lanes);
+  S.n_ftiles = (int32_t)S.ftiles.size();
+  S.tiles = S.ftiles;  // the move sub-step splits these tiles further
+  S.n_tiles = S.n_ftiles;
   S.tiling = tiling_metrics(S.tiles, S.lanes, S.lane0, S.weight);
   S.tiling.n_lanes = S.n_lanes;
   S.tiling.n_cells = S.n_cells;
 
   // ---- host images of the device arrays
-  const NetDims nd = net_dims(p, net);
-  std::vector<int8_t> lanes8(L), rank8(L, 0);
-  std::vector<int32_t> node_in_off(S.n_nodes + 1, 0), node_in(L);
-  for (int32_t i = 0; i < L; ++i) {
-    lanes8[i] = (int8_t)S.lanes[i];
-    if (!S.ring) rank8[i] = net->rank[order[i]];
-    node_in_off[S.to[i] + 1]++;
-  }
-  for (int32_t v = 0; v < S.n_nodes; ++v) node_in_off[v + 1] += node_in_off[v];
-  {
-    std::vector<int32_t> fill(node_in_off.begin(), node_in_off.end() - 1);
-    for (int32_t i = 0; i < L; ++i) node_in[fill[S.to[i]]++] = i;
-    for (int32_t v = 0; v < S.n_nodes; ++v)
-      std::sort(node_in.begin() + node_in_off[v], node_in.begin() + node_in_off[v + 1],
-                [&](int32_t a, int32_t b) { return rank8[a] < rank8[b]; });
-  }
-  std::vector<int32_t> conn_off(L + 1, 0), conn_out;
-  std::vector<int8_t> conn_lo, conn_hi;
+  NetDims nd = net_dims(p, net, c->cfg.back_pieces);
+  if (S.n_lanes >= (1 << 24))
+    return fail(c, SIM_E_CAPACITY, "at most %d lanes per scenario", (1 << 24) - 1);
+  S.conn_off.assign(L + 1, 0);
   if (p->flags & SIM_FLAG_TURN_LANES) {
     for (int32_t i = 0; i < L; ++i) {
       const int32_t e = order[i];
       for (int64_t k = net->conn_off[e]; k < net->conn_off[e + 1]; ++k) {
-        conn_out.push_back(S.int_of[net->conn_out[k]]);
-        conn_lo.push_back(net->conn_lo[k]);
-        conn_hi.push_back(net->conn_hi[k]);
+        S.conn_out.push_back(S.int_of[net->conn_out[k]]);
+        S.conn_lo.push_back(net->conn_lo[k]);
+        S.conn_hi.push_back(net->conn_hi[k]);
       }
-      conn_off[i + 1] = (int32_t)conn_out.size();
+      S.conn_off[i + 1] = (int32_t)S.conn_out.size();
     }
   }
-  std::vector<int32_t> lane_link(S.n_lanes), lane_base(S.n_lanes);
+  std::vector<int4> lane_info(S.n_lanes);
+  S.base.resize(L);
   int64_t rec = 0;
   for (int32_t i = 0; i < L; ++i) {
     const int cap = S.len[i] * (lc_link(*p, S.lanes[i]) ? 2 : 1);
     if (lc_link(*p, S.lanes[i]))
       S.lc_cells = std::max(S.lc_cells, S.lanes[i] * S.len[i]);
+    S.base[i] = (int32_t)rec;
+    const int rank = S.ring ? 0 : net->rank[order[i]];
     for (int k = 0; k < S.lanes[i]; ++k) {
-      lane_link[S.lane0[i] + k] = i;
-      lane_base[S.lane0[i] + k] = (int32_t)rec;
+      lane_info[S.lane0[i] + k] =
+          make_int4((int32_t)rec, (int32_t)lmeta_make(S.len[i], k, S.lanes[i], rank), i, 0);
       rec += cap;
     }
+    if (rec > INT32_MAX) return fail(c, SIM_E_CAPACITY, "too many cells");
   }
-  if (rec > INT32_MAX) return fail(c, SIM_E_CAPACITY, "too many cells");
   S.n_records = rec;
 
   // ---- carve and upload
@@ -430,24 +435,13 @@ extern "C" sim_status sim_load_network(sim_ctx* c, int32_t slot,
   d.n_links = L;
   d.n_lanes = S.n_lanes;
   d.n_tiles = S.n_tiles;
+  d.n_ftiles = S.n_ftiles;
+  d.xcap = S.ring ? 0 : (int32_t)extra_cap(S.n_ftiles, c->cfg.back_pieces);
   d.lc_cells = S.lc_cells;
   d.ring_L = S.ring ? net->len[0] : 0;
   hipStream_t s = c->stream;
-  HIPCHK(c, up(const_cast<int32_t*>(d.link_len), S.len.data(), L, s));
-  HIPCHK(c, up(const_cast<int8_t*>(d.link_lanes), lanes8.data(), L, s));
-  HIPCHK(c, up(const_cast<int32_t*>(d.link_lane0), S.lane0.data(), L, s));
-  HIPCHK(c, up(const_cast<int32_t*>(d.link_to), S.to.data(), L, s));
-  HIPCHK(c, up(const_cast<int8_t*>(d.link_rank), rank8.data(), L, s));
   HIPCHK(c, up(const_cast<int32_t*>(d.link_ext), S.ext_of.data(), L, s));
-  HIPCHK(c, up(const_cast<int32_t*>(d.node_in_off), node_in_off.data(), S.n_nodes + 1, s));
-  HIPCHK(c, up(const_cast<int32_t*>(d.node_in), node_in.data(), L, s));
-  HIPCHK(c, up(const_cast<int32_t*>(d.conn_off), conn_off.data(), L + 1, s));
-  HIPCHK(c, up(const_cast<int32_t*>(d.conn_out), conn_out.data(), (int64_t)conn_out.size(), s));
-  HIPCHK(c, up(const_cast<int8_t*>(d.conn_lo), conn_lo.data(), (int64_t)conn_lo.size(), s));
-  HIPCHK(c, up(const_cast<int8_t*>(d.conn_hi), conn_hi.data(), (int64_t)conn_hi.size(), s));
-  HIPCHK(c, up(const_cast<int32_t*>(d.lane_link), lane_link.data(), S.n_lanes, s));
-  HIPCHK(c, up(const_cast<int32_t*>(d.lane_base), lane_base.data(), S.n_lanes, s));
-  HIPCHK(c, up(const_cast<int2*>(d.tile_lanes), S.tiles.data(), S.n_tiles, s));
+  HIPCHK(c, up(const_cast<int4*>(d.lane_info), lane_info.data(), S.n_lanes, s));
   HIPCHK(c, hipStreamSynchronize(s));
   S.net = true;
   c->work_key.clear();  // slot contents changed: rebuild work lists
@@ -475,9 +469,15 @@ extern "C" sim_status sim_load_vehicles(sim_ctx* c, int32_t slot,
     std::vector<int4> hand_a(S.n_lanes, make_int4(kTagNone, 0, 0, 0));
     HIPCHK(c, up(d.hand_a, hand_a.data(), S.n_lanes, s));
     HIPCHK(c, hipMemsetAsync(d.lane_hc, 0, sizeof(int2) * S.n_lanes, s));
-    HIPCHK(c, hipMemsetAsync(d.tile_ctr, 0, sizeof(long long) * C_N * S.n_tiles, s));
+    HIPCHK(c, hipMemsetAsync(d.tile_ctr, 0, sizeof(long long) * C_N * S.n_lanes, s));
+    HIPCHK(c, hipMemsetAsync(d.ftile_ctr, 0, sizeof(long long) * C_N * S.n_ftiles, s));
+    HIPCHK(c, hipMemsetAsync(d.lane_ends, 0, sizeof(int4) * S.n_lanes, s));
+    HIPCHK(c, hipMemsetAsync(d.xcount, 0, sizeof(int32_t) * 2, s));
+    HIPCHK(c, hipMemsetAsync(d.tile_np, 0, sizeof(int32_t) * S.n_lanes, s));
     HIPCHK(c, hipMemsetAsync(d.ring_ctr, 0, sizeof(long long) * C_N, s));
     HIPCHK(c, hipMemsetAsync(d.err, 0, sizeof(uint32_t), s));
+    std::vector<int32_t> claim(S.n_lanes, INT32_MAX);
+    HIPCHK(c, up(d.claim, claim.data(), S.n_lanes, s));
     HIPCHK(c, hipStreamSynchronize(s));
   }
 
@@ -525,7 +525,10 @@ extern "C" sim_status sim_load_vehicles(sim_ctx* c, int32_t slot,
     if (n > 0 && v->route_off[0] != 0) return fail(c, SIM_E_INVAL, "route_off[0] must be 0");
     if (R > INT32_MAX - 2) return fail(c, SIM_E_CAPACITY, "too many route entries");
     const int32_t L = S.n_links;
+    const bool turn = S.p.flags & SIM_FLAG_TURN_LANES;
+    // route entries as internal link ids, then as route info words
     std::vector<int32_t> rl(R);
+    std::vector<uint32_t> rinfo(R);
     for (int32_t i = 0; i < n; ++i) {
       const int64_t a = v->route_off[i], b = v->route_off[i + 1];
       if (b <= a) return fail(c, SIM_E_INVAL, "vehicle %d: empty route", i);
@@ -536,47 +539,28 @@ extern "C" sim_status sim_load_vehicles(sim_ctx* c, int32_t slot,
         if (j > a && S.to[rl[j - 1]] != S.from[rl[j]])
           return fail(c, SIM_E_INVAL, "vehicle %d: route links not connected", i);
       }
-    }
-    // turn connectivity must exist for every turn a route makes
-    std::vector<int32_t> conn_off;
-    std::vector<int32_t> conn_out;
-    std::vector<int8_t> conn_lo, conn_hi;
-    const bool turn = S.p.flags & SIM_FLAG_TURN_LANES;
-    if (turn) {
-      conn_off.resize(L + 1);
-      HIPCHK(c, hipMemcpyAsync(conn_off.data(), d.conn_off, sizeof(int32_t) * (L + 1),
-                               hipMemcpyDeviceToHost, s));
-      HIPCHK(c, hipStreamSynchronize(s));
-      const int32_t C = conn_off[L];
-      conn_out.resize(C);
-      conn_lo.resize(C);
-      conn_hi.resize(C);
-      HIPCHK(c, hipMemcpyAsync(conn_out.data(), d.conn_out, sizeof(int32_t) * C, hipMemcpyDeviceToHost, s));
-      HIPCHK(c, hipMemcpyAsync(conn_lo.data(), d.conn_lo, C, hipMemcpyDeviceToHost, s));
-      HIPCHK(c, hipMemcpyAsync(conn_hi.data(), d.conn_hi, C, hipMemcpyDeviceToHost, s));
-      HIPCHK(c, hipStreamSynchronize(s));
-    }
-    auto lohi = [&](int32_t link, int32_t nxt, int& lo, int& hi) -> bool {
-      lo = 0;
-      hi = S.lanes[link] - 1;
-      if (!turn || nxt < 0) return true;
-      for (int32_t e = conn_off[link]; e < conn_off[link + 1]; ++e)
-        if (conn_out[e] == nxt) {
-          lo = conn_lo[e];
-          hi = conn_hi[e];
-          return true;
-        }
-      return false;
-    };
-    if (turn)
-      for (int32_t i = 0; i < n; ++i)
-        for (int64_t j = v->route_off[i]; j + 1 < v->route_off[i + 1]; ++j) {
-          int lo, hi;
-          if (!lohi(rl[j], rl[j + 1], lo, hi))
+      for (int64_t j = a; j < b; ++j) {
+        const int32_t link = rl[j];
+        int lo = 0, hi = S.lanes[link] - 1;
+        if (turn && j + 1 < b) {
+          bool found = false;
+          for (int32_t e = S.conn_off[link]; e < S.conn_off[link + 1]; ++e)
+            if (S.conn_out[e] == rl[j + 1]) {
+              lo = S.conn_lo[e];
+              hi = S.conn_hi[e];
+              found = true;
+              break;
+            }
+          if (!found)
             return fail(c, SIM_E_INVAL, "vehicle %d: no lane connectivity for a turn", i);
         }
+        rinfo[j] = rinfo_make(S.lane0[link], S.lanes[link], lo, hi, j + 1 == b);
+      }
+    }
+    auto ninfo_of = [&](int64_t r, int32_t i) -> int32_t {
+      return r + 1 < v->route_off[i + 1] ? (int32_t)rinfo[r + 1] : 0;
+    };
     // initial state: active vehicles into their lanes, lead first
-    std::vector<int32_t> cnt(S.n_lanes, 0);
     std::vector<int32_t> wait_cnt(L + 1, 0);
     std::vector<int32_t> act;
     for (int32_t i = 0; i < n; ++i) {
@@ -592,36 +576,32 @@ extern "C" sim_status sim_load_vehicles(sim_ctx* c, int32_t slot,
         if (k < 0 || k >= S.lanes[link] || v->init_x[i] < 0 ||
             v->init_x[i] >= S.len[link] || v->init_v[i] < 0 || v->init_v[i] > vmax)
           return fail(c, SIM_E_INVAL, "vehicle %d: placement out of range", i);
-        cnt[S.lane0[link] + k]++;
         act.push_back(i);
       } else if (stt != 2) {
         return fail(c, SIM_E_INVAL, "vehicle %d: bad status", i);
       }
     }
-    auto lane_of = [&](int32_t i) {
-      return S.lane0[rl[v->route_off[i] + v->init_rptr[i]]] + v->init_lane[i];
-    };
+    auto link_of = [&](int32_t i) { return rl[v->route_off[i] + v->init_rptr[i]]; };
+    auto lane_of = [&](int32_t i) { return S.lane0[link_of(i)] + v->init_lane[i]; };
     std::sort(act.begin(), act.end(), [&](int32_t a, int32_t b) {
       const int32_t qa = lane_of(a), qb = lane_of(b);
       if (qa != qb) return qa < qb;
       return v->init_x[a] > v->init_x[b];
     });
-    std::vector<int32_t> lane_base(S.n_lanes);
     std::vector<int2> hc(S.n_lanes, make_int2(0, 0));
-    HIPCHK(c, hipMemcpyAsync(lane_base.data(), d.lane_base, sizeof(int32_t) * S.n_lanes,
-                             hipMemcpyDeviceToHost, s));
-    HIPCHK(c, hipStreamSynchronize(s));
-    // records are written sparsely: stage them and upload per lane run
+    std::vector<int4> ends(S.n_lanes, make_int4(0, 0, 0, 0));
+    // records of each lane's run are contiguous from the lane's base
     std::vector<uint2> hot;
     std::vector<int2> cold;
-    std::vector<int64_t> run_slot;  // first slot of each lane run
+    std::vector<int64_t> run_slot;
     std::vector<int32_t> run_len, run_first;
     for (size_t a = 0; a < act.size();) {
       const int32_t qq = lane_of(act[a]);
       size_t b = a;
       while (b < act.size() && lane_of(act[b]) == qq) ++b;
-      const int32_t link = rl[v->route_off[act[a]] + v->init_rptr[act[a]]];
-      run_slot.push_back(lane_base[qq]);
+      const int32_t link = link_of(act[a]);
+      run_slot.push_back(S.base[link] + (int64_t)(qq - S.lane0[link]) *
+                                            (S.len[link] * (lc_link(S.p, S.lanes[link]) ? 2 : 1)));
       run_len.push_back((int32_t)(b - a));
       run_first.push_back((int32_t)hot.size());
       for (size_t j = a; j < b; ++j) {
@@ -629,19 +609,18 @@ extern "C" sim_status sim_load_vehicles(sim_ctx* c, int32_t slot,
         if (j > a && v->init_x[act[j - 1]] == v->init_x[i])
           return fail(c, SIM_E_INVAL, "vehicles %d and %d share a cell", act[j - 1], i);
         const int64_t rp = v->route_off[i] + v->init_rptr[i];
-        const int32_t nxt = rp + 1 < v->route_off[i + 1] ? rl[rp + 1] : -1;
-        int lo, hi;
-        lohi(link, nxt, lo, hi);
-        hot.push_back(make_uint2(pack_xvf(v->init_x[i], v->init_v[i], fl_make(nxt < 0, lo, hi)),
+        hot.push_back(make_uint2(pack_xvf(v->init_x[i], v->init_v[i], rinfo_flags(rinfo[rp])),
                                  (uint32_t)i));
-        cold.push_back(make_int2((int32_t)rp, nxt));
+        cold.push_back(make_int2((int32_t)rp, ninfo_of(rp, i)));
       }
       hc[qq] = make_int2(0, (int32_t)(b - a));
+      ends[qq] = make_int4((int)hot[run_first.back()].x, cold[run_first.back()].y,
+                           (int)hot.back().x, 0);
       a = b;
     }
     // parking queues ordered by (depart, id)
     for (int32_t l = 0; l < L; ++l) wait_cnt[l + 1] += wait_cnt[l];
-    std::vector<int32_t> wid(wait_cnt[L]), wdep(wait_cnt[L]);
+    std::vector<int32_t> wid(wait_cnt[L]);
     {
       std::vector<int32_t> fill(wait_cnt.begin(), wait_cnt.end() - 1);
       for (int32_t i = 0; i < n; ++i)
@@ -652,7 +631,14 @@ extern "C" sim_status sim_load_vehicles(sim_ctx* c, int32_t slot,
                     if (v->depart[a] != v->depart[b]) return v->depart[a] < v->depart[b];
                     return a < b;
                   });
-      for (size_t j = 0; j < wid.size(); ++j) wdep[j] = v->depart[wid[j]];
+    }
+    std::vector<int4> wrec(wid.size());
+    std::vector<int32_t> winfo0(wid.size());
+    for (size_t j = 0; j < wid.size(); ++j) {
+      const int32_t i = wid[j];
+      const int64_t r0 = v->route_off[i];
+      wrec[j] = make_int4(i, v->depart[i], (int32_t)r0, ninfo_of(r0, i));
+      winfo0[j] = (int32_t)rinfo[r0];
     }
     std::vector<int32_t> exit_t(R, -1);
     if (v->exit_t0) std::copy(v->exit_t0, v->exit_t0 + R, exit_t.begin());
@@ -665,18 +651,19 @@ extern "C" sim_status sim_load_vehicles(sim_ctx* c, int32_t slot,
     d.n_veh = n;
     d.n_route = R;
     d.t = v->t0;
-    HIPCHK(c, up(const_cast<int32_t*>(d.wait_id), wid.data(), (int64_t)wid.size(), s));
-    HIPCHK(c, up(const_cast<int32_t*>(d.wait_dep), wdep.data(), (int64_t)wdep.size(), s));
+    HIPCHK(c, up(const_cast<int4*>(d.wait_rec), wrec.data(), (int64_t)wrec.size(), s));
+    HIPCHK(c, up(const_cast<int32_t*>(d.wait_info0), winfo0.data(), (int64_t)winfo0.size(), s));
     HIPCHK(c, up(const_cast<int32_t*>(d.wait_off), wait_cnt.data(), L + 1, s));
     HIPCHK(c, up(d.wait_head, wait_cnt.data(), L, s));
     HIPCHK(c, up(const_cast<int64_t*>(d.route_off), v->route_off, n + 1, s));
-    HIPCHK(c, up(const_cast<int32_t*>(d.route_links), rl.data(), R, s));
+    HIPCHK(c, up(const_cast<uint32_t*>(d.route_info), rinfo.data(), R, s));
     HIPCHK(c, up(d.exit_t, exit_t.data(), R, s));
     for (size_t r = 0; r < run_slot.size(); ++r) {
       HIPCHK(c, up(d.hot + run_slot[r], hot.data() + run_first[r], run_len[r], s));
       HIPCHK(c, up(d.cold + run_slot[r], cold.data() + run_first[r], run_len[r], s));
     }
     HIPCHK(c, up(d.lane_hc, hc.data(), S.n_lanes, s));
+    HIPCHK(c, up(d.lane_ends, ends.data(), S.n_lanes, s));
     HIPCHK(c, hipStreamSynchronize(s));
     S.n_route = R;
   }
@@ -699,19 +686,31 @@ sim_status build_work(sim_ctx* c, const std::vector<int32_t>& net,
   key.insert(key.end(), ring.begin(), ring.end());
   if (key == c->work_key) return SIM_OK;
   // all tiles of all network slots, dealt to the 8 XCDs in contiguous chunks
-  // (workgroup w runs on XCD w mod 8)
-  std::vector<int2> all;
+  // (workgroup w runs on XCD w mod 8); front tiles first, then back tiles
   int lc = 0;
+  std::vector<int2> all;
   for (int32_t sl : net) {
     const Slot& S = c->slots[sl];
-    for (int32_t t = 0; t < S.n_tiles; ++t) all.push_back(make_int2(sl, t));
+    for (int32_t t = 0; t < S.n_ftiles; ++t) all.push_back(make_int2(sl, t));
     lc = std::max(lc, S.lc_cells);
   }
-  const std::vector<int2> work = xcd_interleave(all, 8);
+  const std::vector<int2> dealt = xcd_interleave(all, 8);
+  std::vector<int4> work(dealt.size());
+  for (size_t k = 0; k < dealt.size(); ++k) {
+    const int2 tl = c->slots[dealt[k].x].ftiles[dealt[k].y];
+    work[k] = make_int4(dealt[k].x, tl.x, tl.y, dealt[k].y);
+  }
+  c->single_slot = net.size() == 1 ? net[0] : -1;
+  c->n_extra = c->single_slot >= 0 ? c->slots[c->single_slot].d.xcap : 0;
+  if (c->graph) {
+    (void)hipGraphExecDestroy(c->graph);
+    c->graph = nullptr;
+    c->graph_k = 0;
+  }
   if (work.size() > c->work_cap) {
     if (c->d_work) HIPCHK(c, hipFree(c->d_work));
     c->d_work = nullptr;
-    HIPCHK(c, hipMalloc(&c->d_work, sizeof(int2) * std::max<size_t>(work.size(), 1)));
+    HIPCHK(c, hipMalloc(&c->d_work, sizeof(int4) * std::max<size_t>(work.size(), 1)));
     c->work_cap = work.size();
   }
   std::vector<int32_t> list(net);
@@ -730,6 +729,56 @@ sim_status build_work(sim_ctx* c, const std::vector<int32_t>& net,
   c->n_ring = (int)ring.size();
   c->lc_cells = lc;
   c->work_key = key;
+  return SIM_OK;
+}
+
+// A HIP graph of K steps of the current work list (two kernels per step) and
+// the advance of t by K, built node by node (the caller's stream may be the
+// legacy default stream, which cannot be captured).
+sim_status build_graph(sim_ctx* c, int K) {
+  hipGraph_t g = nullptr;
+  HIPCHK(c, hipGraphCreate(&g, 0));
+  const bool batched = c->single_slot < 0;
+  int slot = batched ? 0 : c->single_slot;
+  int pieces = batched ? 1 : c->cfg.back_pieces;
+  int n_work = c->n_work;
+  const DevScen* descs = c->d_descs;
+  const int4* work = c->d_work;
+  hipGraphNode_t prev = nullptr;
+  hipError_t e = hipSuccess;
+  auto add = [&](void* fn, int grid, int block, size_t shmem, void** args) {
+    if (e != hipSuccess) return;
+    hipKernelNodeParams kp{};
+    kp.func = fn;
+    kp.gridDim = dim3(grid);
+    kp.blockDim = dim3(block);
+    kp.sharedMemBytes = (unsigned)shmem;
+    kp.kernelParams = args;
+    kp.extra = nullptr;
+    hipGraphNode_t node;
+    e = hipGraphAddKernelNode(&node, g, prev ? &prev : nullptr, prev ? 1 : 0, &kp);
+    prev = node;
+  };
+  for (int s = 0; s < K; ++s) {
+    int step = s;
+    void* fa[] = {&descs, &slot, &work, &pieces, &step};
+    add(front_kernel(batched), c->n_work, kFrontThreads, (size_t)3 * c->lc_cells, fa);
+    void* ba[] = {&descs, &slot, &work, &n_work, &step};
+    add(back_kernel(batched), c->n_work + (batched ? 0 : c->n_extra),
+        kBackThreadsPerPiece, 0, ba);
+  }
+  DevScen* mdescs = c->d_descs;
+  const int* list = c->d_list;
+  int n = c->n_net, k = K;
+  void* aa[] = {&mdescs, &list, &n, &k};
+  add(advance_kernel(), (n + 63) / 64, 64, 0, aa);
+  hipGraphExec_t ex = nullptr;
+  if (e == hipSuccess) e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) return fail(c, SIM_E_DEVICE, "graph: %s", hipGetErrorString(e));
+  if (c->graph) (void)hipGraphExecDestroy(c->graph);
+  c->graph = ex;
+  c->graph_k = K;
   return SIM_OK;
 }
 
@@ -800,17 +849,30 @@ extern "C" sim_status sim_step(sim_ctx* c, const int32_t* slots, int32_t n_slots
   sim_status st = build_work(c, net, ring);
   if (st != SIM_OK) return st;
   if (!net.empty()) {
-    for (int32_t s = 0; s < n_steps; ++s) {
+    const int K = c->cfg.graph_steps;
+    int32_t done = 0;
+    if (K > 0 && !c->profile && n_steps >= K) {
+      if (!c->graph || c->graph_k != K) {
+        st = build_graph(c, K);
+        if (st != SIM_OK) return st;
+      }
+      for (; done + K <= n_steps; done += K) HIPCHK(c, hipGraphLaunch(c->graph, c->stream));
+    }
+    const int32_t rest = n_steps - done;
+    for (int32_t s = 0; s < rest; ++s) {
       st = timed(c, 0, [&] {
-        return launch_front(c->d_descs, c->d_work, c->n_work, s, c->lc_cells, c->stream);
+        return launch_front(c->d_descs, c->single_slot, c->d_work, c->n_work,
+                            c->cfg.back_pieces, s, c->lc_cells, c->stream);
       });
       if (st != SIM_OK) return st;
       st = timed(c, 1, [&] {
-        return launch_back(c->d_descs, c->d_work, c->n_work, s, c->stream);
+        return launch_back(c->d_descs, c->single_slot, c->d_work, c->n_work,
+                           c->n_extra, s, c->stream);
       });
       if (st != SIM_OK) return st;
     }
-    HIPCHK(c, launch_advance(c->d_descs, c->d_list, c->n_net, n_steps, c->stream));
+    if (rest > 0)
+      HIPCHK(c, launch_advance(c->d_descs, c->d_list, c->n_net, rest, c->stream));
   }
   if (!ring.empty()) {
     st = timed(c, 2, [&] {
@@ -909,24 +971,38 @@ extern "C" sim_status sim_link_costs(sim_ctx* c, int32_t slot, float* out) {
   const Slot& S = c->slots[slot];
   if (!S.net) return fail(c, SIM_E_STATE, "slot %d has no network", slot);
   if (!out) return fail(c, SIM_E_INVAL, "out is NULL");
-  std::vector<long long> ctr((size_t)S.n_tiles * C_N);
-  HIPCHK(c, hipMemcpyAsync(ctr.data(), S.d.tile_ctr, sizeof(long long) * ctr.size(),
-                           hipMemcpyDeviceToHost, c->stream));
-  HIPCHK(c, hipStreamSynchronize(c->stream));
-  for (int32_t t = 0; t < S.n_tiles; ++t) {
-    const int2 tl = S.tiles[t];
-    double cells = 0;
-    std::vector<int32_t> links;
-    for (int32_t q = tl.x; q < tl.x + tl.y; ++q) {
-      // lanes of one link are contiguous; collect each link once
-      int32_t lk = (int32_t)(std::upper_bound(S.lane0.begin(), S.lane0.end(), q) -
-                             S.lane0.begin()) - 1;
-      if (links.empty() || links.back() != lk) links.push_back(lk);
+  std::fill(out, out + S.n_links, 0.0f);
+  // cycles of each tile of both sub-steps, shared out over its links by cells
+  for (int pass = 0; pass < 2; ++pass) {
+    // move-tile counters sit at the entry of each tile's first lane (the
+    // tiles may have been rebalanced); they are credited to the static tile
+    // holding that lane.  Lane-change tiles use one entry per tile.
+    const std::vector<int2>& tiles = pass == 0 ? S.tiles : S.ftiles;
+    const size_t entries = pass == 0 ? (size_t)S.n_lanes : tiles.size();
+    std::vector<long long> ctr(entries * C_N);
+    HIPCHK(c, hipMemcpyAsync(ctr.data(), pass == 0 ? S.d.tile_ctr : S.d.ftile_ctr,
+                             sizeof(long long) * ctr.size(), hipMemcpyDeviceToHost,
+                             c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (size_t t = 0; t < tiles.size(); ++t) {
+      const int2 tl = tiles[t];
+      double cyc = 0;
+      if (pass == 0) {
+        for (int32_t q = tl.x; q < tl.x + tl.y; ++q) cyc += (double)ctr[(size_t)q * C_N + C_CYCLES];
+      } else {
+        cyc = (double)ctr[t * C_N + C_CYCLES];
+      }
+      const int32_t l0 = (int32_t)(std::upper_bound(S.lane0.begin(), S.lane0.end(), tl.x) -
+                                   S.lane0.begin()) - 1;
+      double cells = 0;
+      int32_t l1 = l0;
+      while (l1 < S.n_links && S.lane0[l1] < tl.x + tl.y) {
+        cells += (double)S.len[l1] * S.lanes[l1];
+        ++l1;
+      }
+      for (int32_t lk = l0; lk < l1; ++lk)
+        out[S.ext_of[lk]] += (float)(cells > 0 ? cyc * S.len[lk] * S.lanes[lk] / cells : 0);
     }
-    for (int32_t lk : links) cells += (double)S.len[lk] * S.lanes[lk];
-    const double cyc = (double)ctr[(size_t)t * C_N + C_CYCLES];
-    for (int32_t lk : links)
-      out[S.ext_of[lk]] = (float)(cells > 0 ? cyc * S.len[lk] * S.lanes[lk] / cells : 0);
   }
   return SIM_OK;
 }

@@ -33,6 +33,7 @@ class SimError(RuntimeError):
 class sim_config(C.Structure):
     _fields_ = [("abi_version", C.c_int32), ("max_slots", C.c_int32),
                 ("stream", C.c_void_p), ("tile_lanes", C.c_int32),
+                ("back_pieces", C.c_int32), ("graph_steps", C.c_int32),
                 ("reserved", C.c_int32)]
 
 
@@ -173,7 +174,8 @@ class _Inputs:
 class Context:
     """A libtransims context on the current GPU with `max_slots` slots."""
 
-    def __init__(self, max_slots: int = 1, tile_lanes: int = 0, stream=None):
+    def __init__(self, max_slots: int = 1, tile_lanes: int = 0,
+                 back_pieces: int = 0, graph_steps: int = 0, stream=None):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("libtransims needs a GPU; none is visible")
@@ -183,7 +185,7 @@ class Context:
             stream = torch.cuda.current_stream()
         self.stream = stream
         cfg = sim_config(ABI_VERSION, max_slots, C.c_void_p(stream.cuda_stream),
-                         tile_lanes, 0)
+                         tile_lanes, back_pieces, graph_steps, 0)
         h = C.c_void_p()
         self._check(self.lib.sim_create(C.byref(cfg), C.byref(h)), None)
         self.h = h

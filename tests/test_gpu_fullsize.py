@@ -1,0 +1,46 @@
+"""Full-size parity on the Portland-sized network (20,024 links, 200,000
+vehicles, 3,600 steps) in the configuration the benchmark times: the GPU run
+and the CPU oracle must end in the same state, vehicle by vehicle, with the
+same exit times and counters."""
+import pytest
+
+import oracle
+from paper_cs_0105004_amd import scenarios as S
+
+from parity import assert_same_state, assert_same_stats
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def portland():
+    return S.portland_like()
+
+
+def test_portland_full_run_matches_oracle(portland):
+    from paper_cs_0105004_amd.sim import Context
+    ctx = Context(max_slots=1)  # the benchmark's default launch configuration
+    ctx.load(0, portland)
+    orc = oracle.OracleSim(portland)
+    for upto in (900, 1800, 3600):
+        ctx.step(0, upto - ctx.stats(0)["t"])
+        orc.step(upto - orc.stats()["t"])
+        print("portland step", upto, flush=True)
+        assert_same_stats(ctx.stats(0), orc.stats(), f"portland t={upto}")
+    assert_same_state(ctx.state(0), orc.state(), "portland end")
+    ctx.close()
+
+
+@pytest.mark.parametrize("pieces,graph", [(1, -1), (8, 200)])
+def test_portland_configs_agree(portland, pieces, graph):
+    from paper_cs_0105004_amd.sim import Context
+    ref = Context(max_slots=1)
+    alt = Context(max_slots=1, back_pieces=pieces, graph_steps=graph)
+    ref.load(0, portland)
+    alt.load(0, portland)
+    ref.step(0, 1500)
+    alt.step(0, 1500)
+    assert_same_stats(alt.stats(0), ref.stats(0), "configs")
+    assert_same_state(alt.state(0), ref.state(0), "configs")
+    ref.close()
+    alt.close()

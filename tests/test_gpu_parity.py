@@ -103,10 +103,13 @@ def test_lane_change_slowdown_draws(sim):
     run_side_by_side(sim, 0, scen, 300, every=25)
 
 
-@pytest.mark.parametrize("tile_lanes", [1, 4, 37, 64])
-def test_tile_size_does_not_change_results(tile_lanes):
+@pytest.mark.parametrize("tile_lanes,pieces,graph",
+                         [(1, 1, -1), (4, 8, 5), (37, 3, 1), (64, 8, 64),
+                          (16, 4, 64), (16, 1, 7)])
+def test_tile_size_does_not_change_results(tile_lanes, pieces, graph):
     from paper_cs_0105004_amd.sim import Context
-    ctx = Context(max_slots=1, tile_lanes=tile_lanes)
+    ctx = Context(max_slots=1, tile_lanes=tile_lanes, back_pieces=pieces,
+                  graph_steps=graph)
     try:
         run_side_by_side(ctx, 0, small_grid(S.FLAG_LANE_CHANGE, seed=7), 250,
                          every=50)
@@ -148,3 +151,19 @@ def test_restart_from_saved_state(sim):
     o = oracle.OracleSim(scen)
     o.step(270)
     assert_same_state(end, o.state(), "restart vs oracle")
+
+
+@pytest.mark.parametrize("tile_lanes,pieces,flags", [(64, 1, 0), (64, 1, S.FLAG_LANE_CHANGE),
+                                                     (16, 4, 0), (3, 2, S.FLAG_LANE_CHANGE)])
+def test_dense_lanes_many_vehicle_groups(tile_lanes, pieces, flags):
+    # lanes holding hundreds of vehicles: one wavefront updates them in many
+    # groups of 64, rear first, so every vehicle must still see the old
+    # position of the one ahead
+    from paper_cs_0105004_amd.sim import Context
+    scen = S.loop_of_links([700, 650, 900], 450, vmax=5, p="0.25", seed=9,
+                           T=120, lanes=3, placement_seed=4, flags=flags)
+    ctx = Context(max_slots=1, tile_lanes=tile_lanes, back_pieces=pieces)
+    try:
+        run_side_by_side(ctx, 0, scen, 120, every=20, full_at=(1, 60))
+    finally:
+        ctx.close()
