@@ -54,13 +54,9 @@ __device__ __forceinline__ int wrapi(int a, int cap) {
   return a >= cap ? a - cap : a;
 }
 
-// lane header word: head index (bits 0-15) and buffer parity (bit 16)
-__device__ __forceinline__ int hp_head(int hp) { return hp & 0xFFFF; }
-__device__ __forceinline__ int hp_par(int hp) { return hp >> 16; }
-
-// record slot of the j-th vehicle (0 = lead) of a lane
-__device__ __forceinline__ int rec_slot(int base, int hp, int len, int j) {
-  return base + hp_par(hp) * len + wrapi(hp_head(hp) + j, len);
+// record slot of the j-th vehicle (0 = lead) of a lane with queue word hc
+__device__ __forceinline__ int rec_slot(int base, int hc, int len, int j) {
+  return base + hc_par(hc) * len + wrapi(hc_head(hc) + j, len);
 }
 
 __device__ __forceinline__ unsigned long long wave_sum(unsigned long long v) {
@@ -195,7 +191,7 @@ __device__ int lane_change_tile(const DevScen& S, int t, int nl,
     moved = (int)wave_sum((unsigned long long)moved);
     __syncthreads();
     if (moved > 0) {
-      const int npar = 1 - hp_par(s_hp[tb]);
+      const int npar = 1 - hc_par(s_hp[tb]);
       for (int k = 0; k < lanes; ++k) {
         const int dst0 = s_info[tb + k].x + npar * len;
         int n = 0;
@@ -211,7 +207,7 @@ __device__ int lane_change_tile(const DevScen& S, int t, int nl,
           n += __popcll(m);
         }
         if (i == 0) {
-          s_hp[tb + k] = npar << 16;
+          s_hp[tb + k] = hc_make(0, npar, 0);
           s_cnt[tb + k] = n;
         }
       }
@@ -242,99 +238,93 @@ __global__ __launch_bounds__(kWave) void k_front(
   const int t = S.t + step;
   const int vmax = S.vmax;
   const GAS v4i* __restrict__ lane_info = gpv<v4i>(S.lane_info);
-  GAS v2i* __restrict__ lane_hc = gpv<v2i>(S.lane_hc);
+  const GAS v4i* __restrict__ lane_state = gpv<v4i>(S.lane_state);
   GAS v4i* __restrict__ lane_sum = gpv<v4i>(S.lane_sum);
-  const GAS v4i* __restrict__ lane_ends = gpv<v4i>(S.lane_ends);
   GAS int32_t* __restrict__ claim_a = gp(S.claim);
   const GAS v4i* __restrict__ hand_a = gpv<v4i>(S.hand_a);
   const GAS int32_t* __restrict__ hand_b = gp(S.hand_b);
+  GAS int32_t* __restrict__ lane_qhead = gp(S.lane_qhead);
+  GAS v4i* __restrict__ lane_qrec = gpv<v4i>(S.lane_qrec);
   // the lane-change pass reaches the records through the descriptor too
   GAS v2u* hot = gpv<v2u>(S.hot);
   GAS v2i* cold = gpv<v2i>(S.cold);
-  const GAS int32_t* __restrict__ wait_off = gp(S.wait_off);
-  const GAS v4i* __restrict__ wait_rec = gpv<v4i>(S.wait_rec);
-  const GAS int32_t* __restrict__ wait_info0 = gp(S.wait_info0);
-  GAS int32_t* __restrict__ wait_head = gp(S.wait_head);
   const int i = threadIdx.x;
   const int nl = w.z;
   const bool act = i < nl;
   const int gid = w.y + i;
 
-  v4i info = {0, 0, 0, 0};
-  int hp = 0, cnt = 0, len = 1, k = 0, lanes = 1;
-  uint32_t rear_w = 0, lead_w = 0;
-  int lead_ninfo = 0;
-  bool empty0 = false;
+  // everything this kernel reads of a lane, in one round of loads
+  v4i info = {0, 0, 0, 0}, st = {0, 0, 0, 0}, ha = {0, 0, 0, 0};
+  v4i qrec = {-1, 0, 0, 0};
+  int hb = 0, qhead = 0;
   if (act) {
     info = lane_info[gid];
-    const v2i hc = lane_hc[gid];
-    const v4i ends = lane_ends[gid];
-    const v4i ha = hand_a[gid];
-    const int hb = hand_b[gid];
-    hp = hc.x;
-    cnt = hc.y;
-    const uint32_t meta = (uint32_t)info.y;
-    len = lmeta_len(meta);
-    k = lmeta_k(meta);
-    lanes = lmeta_lanes(meta);
-    const int base = info.x;
-    // the lane's two end records as the move left them
-    lead_w = (uint32_t)ends.x;
-    lead_ninfo = ends.y;
-    rear_w = (uint32_t)ends.z;
-    // the vehicle the upstream node handed over in the previous step
-    if (ha.x == t - 1) {
-      if (cnt >= len) {
-        atomicOr(S.err, SIM_DEVERR_LANE_FULL);
-      } else {
-        const int slot = rec_slot(base, hp, len, cnt);
-        hot[slot] = (v2u){(uint32_t)ha.y, (uint32_t)ha.z};
-        cold[slot] = (v2i){ha.w, hb};
-        rear_w = (uint32_t)ha.y;
-        if (cnt == 0) {
-          lead_w = rear_w;
-          lead_ninfo = hb;
-        }
-        ++cnt;
+    st = lane_state[gid];
+    ha = hand_a[gid];
+    hb = hand_b[gid];
+    qhead = lane_qhead[gid];
+    qrec = lane_qrec[gid];
+  }
+  const uint32_t meta = (uint32_t)info.y;
+  const int len = act ? lmeta_len(meta) : 1;
+  const int k = lmeta_k(meta), lanes = lmeta_lanes(meta);
+  const int base = info.x;
+  int head = hc_head(st.w), par = hc_par(st.w), cnt = act ? hc_cnt(st.w) : 0;
+  uint32_t lead_w = (uint32_t)st.x, rear_w = (uint32_t)st.z;
+  int lead_ninfo = st.y;
+
+  // the vehicle the upstream node handed over in the previous step
+  if (act && ha.x == t - 1) {
+    if (cnt >= len) {
+      atomicOr(S.err, SIM_DEVERR_LANE_FULL);
+    } else {
+      const int slot = rec_slot(base, st.w, len, cnt);
+      hot[slot] = (v2u){(uint32_t)ha.y, (uint32_t)ha.z};
+      cold[slot] = (v2i){ha.w, hb};
+      rear_w = (uint32_t)ha.y;
+      if (cnt == 0) {
+        lead_w = rear_w;
+        lead_ninfo = hb;
       }
+      ++cnt;
     }
-    empty0 = cnt == 0 || xvf_x(rear_w) != 0;
   }
   // parking: the lowest lane of the link whose cell 0 is empty takes the
-  // head of the link's queue if it has departed
-  const unsigned long long free0 = __ballot(act && empty0);
+  // head of the link's queue if it has departed.  The queue is kept with the
+  // link's lane 0, whose thread shares it.
+  const bool empty0 = act && (cnt == 0 || xvf_x(rear_w) != 0);
+  const unsigned long long free0 = __ballot(empty0);
+  const int l0 = i - k;  // this link's lane 0 in the tile
+  const int qh = __shfl(qhead, l0);
+  const int qid = __shfl(qrec.x, l0), qdep = __shfl(qrec.y, l0),
+            qrp = __shfl(qrec.z, l0), qni = __shfl(qrec.w, l0);
   int ins = 0;
-  if (act && empty0) {
-    const unsigned long long lm = (free0 >> (i - k)) & ((1ull << lanes) - 1ull);
-    if (__builtin_ctzll(lm) == k) {
-      const int link = info.z;
-      const int h = wait_head[link];
-      const int hend = wait_off[link + 1];
-      const int hq = h < hend ? h : 0;  // a valid index either way
-      const v4i wr = wait_rec[hq];
-      const uint32_t info0 = (uint32_t)wait_info0[hq];
-      if (h < hend && wr.y <= t) {
-        {
-          wait_head[link] = h + 1;
-          rear_w = pack_xvf(0, 0, rinfo_flags(info0));
-          const int slot = rec_slot(info.x, hp, len, cnt);
-          hot[slot] = (v2u){rear_w, (uint32_t)wr.x};
-          cold[slot] = (v2i){wr.z, wr.w};
-          if (cnt == 0) {
-            lead_w = rear_w;
-            lead_ninfo = wr.w;
-          }
-          ++cnt;
-          ins = 1;
-        }
+  if (empty0) {
+    const unsigned long long lm = (free0 >> l0) & ((1ull << lanes) - 1ull);
+    if (__builtin_ctzll(lm) == k && qh < info.w && qid >= 0 &&
+        (qdep & ((1 << kDepartBits) - 1)) <= t) {
+      rear_w = pack_xvf(0, 0, (uint32_t)qdep >> kDepartBits);
+      const int slot = rec_slot(base, st.w, len, cnt);
+      hot[slot] = (v2u){rear_w, (uint32_t)qid};
+      cold[slot] = (v2i){qrp, qni};
+      if (cnt == 0) {
+        lead_w = rear_w;
+        lead_ninfo = qni;
       }
+      ++cnt;
+      ins = 1;
     }
+  }
+  const unsigned long long insm = __ballot(ins);
+  if (act && k == 0 && ((insm >> i) & ((1ull << lanes) - 1ull)) != 0) {
+    lane_qhead[gid] = qhead + 1;
+    lane_qrec[gid] = (v4i){-1, 0, 0, 0};  // the move kernel fetches the next
   }
   int lc_moves = 0;
   if (S.flags & SIM_FLAG_LANE_CHANGE) {
     if (act) {
       s_info[i] = make_int4(info.x, info.y, info.z, info.w);
-      s_hp[i] = hp;
+      s_hp[i] = hc_make(head, par, 0);
       s_cnt[i] = cnt;
     }
     __syncthreads();
@@ -343,14 +333,16 @@ __global__ __launch_bounds__(kWave) void k_front(
         reinterpret_cast<signed char*>(dyn) + (size_t)2 * S.lc_cells;
     lc_moves = lane_change_tile(S, t, nl, s_info, s_hp, s_cnt, lat, dec);
     __syncthreads();
-    if (act && lc_moves > 0 && hp != s_hp[i]) {
-      hp = s_hp[i];
+    if (act && lc_moves > 0 && hc_make(head, par, 0) != s_hp[i]) {
+      head = hc_head(s_hp[i]);
+      par = hc_par(s_hp[i]);
       cnt = s_cnt[i];
       if (cnt > 0) {
-        const int ls = rec_slot(info.x, hp, len, 0);
+        const int hc = hc_make(head, par, 0);
+        const int ls = rec_slot(base, hc, len, 0);
         lead_w = hot[ls].x;
         lead_ninfo = cold[ls].y;
-        rear_w = hot[rec_slot(info.x, hp, len, cnt - 1)].x;
+        rear_w = hot[rec_slot(base, hc, len, cnt - 1)].x;
       }
     }
   }
@@ -365,11 +357,10 @@ __global__ __launch_bounds__(kWave) void k_front(
         tgt = rinfo_lane0(ni) + min(k, rinfo_lanes(ni) - 1);
         // priority among the candidates aiming at one lane: smallest
         // (rank of the link, lane); they all enter the same node
-        atomicMin((int*)&claim_a[tgt], lmeta_rank((uint32_t)info.y) * 8 + k);
+        atomicMin((int*)&claim_a[tgt], lmeta_rank(meta) * 8 + k);
       }
     }
-    lane_sum[gid] = (v4i){tgt, rear_x, hp, cnt};
-    lane_hc[gid] = (v2i){hp, cnt};
+    lane_sum[gid] = (v4i){tgt, rear_x, hc_make(head, par, cnt), 0};
   }
   // runs of this tile for the move sub-step: a tile heavier than
   // kPieceCost gets more wavefronts, listed for the move kernel
@@ -380,10 +371,10 @@ __global__ __launch_bounds__(kWave) void k_front(
     if (i == 0) {
       int got = 0;
       if (np > 1) {
-        const int base = atomicAdd(&S.xcount[t & 1], np - 1);
-        got = max(0, min(S.xcap - base, np - 1));
+        const int xb = atomicAdd(&S.xcount[t & 1], np - 1);
+        got = max(0, min(S.xcap - xb, np - 1));
         for (int r = 0; r < got; ++r)
-          S.xlist[base + r] =
+          S.xlist[xb + r] =
               make_int4(w.y, w.z | ((r + 1) << 8) | ((got + 1) << 16), w.w, 0);
       }
       S.tile_np[w.w] = got + 1;
@@ -454,9 +445,11 @@ __global__ __launch_bounds__(kWave) void k_back(
   const uint32_t key0 = S.key0, key1 = S.key1;
   const uint64_t slow_thr = S.slow_thr;
   const GAS v4i* __restrict__ lane_info = gpv<v4i>(S.lane_info);
-  GAS v2i* __restrict__ lane_hc = gpv<v2i>(S.lane_hc);
   const GAS v4i* __restrict__ lane_sum = gpv<v4i>(S.lane_sum);
-  GAS v4i* __restrict__ lane_ends = gpv<v4i>(S.lane_ends);
+  GAS v4i* __restrict__ lane_state = gpv<v4i>(S.lane_state);
+  GAS int32_t* __restrict__ lane_qhead = gp(S.lane_qhead);
+  GAS v4i* __restrict__ lane_qrec = gpv<v4i>(S.lane_qrec);
+  const GAS v4i* __restrict__ wait_rec = gpv<v4i>(S.wait_rec);
   GAS int32_t* __restrict__ claim_a = gp(S.claim);
   GAS v4i* __restrict__ hand_a = gpv<v4i>(S.hand_a);
   GAS int32_t* __restrict__ hand_b = gp(S.hand_b);
@@ -477,15 +470,18 @@ __global__ __launch_bounds__(kWave) void k_back(
   // this one may still be reading, so the split must not depend on it.
   int cnt = 0;
   v4i sum = {-1, 0, 0, 0};
-  v4i info = {0, 0, 0, 0};
+  v4i info = {0, 0, 0, 0}, qrec = {0, 0, 0, 0};
+  int qhead = 0;
   if (i < nl) {
     sum = lane_sum[gid];
     info = lane_info[gid];
+    qhead = lane_qhead[gid];
+    qrec = lane_qrec[gid];
   }
   // this wavefront's run of lanes
   bool act = false;
   {
-    const int cost = i < nl ? sum.w + kLaneCost : 0;
+    const int cost = i < nl ? hc_cnt(sum.z) + kLaneCost : 0;
     int ci = cost;
 #pragma unroll
     for (int off = 1; off < kWave; off <<= 1) {
@@ -498,9 +494,15 @@ __global__ __launch_bounds__(kWave) void k_back(
     if (__ballot(act) == 0ull) return;  // no run for this wavefront
   }
   int len = 1, hp = 0;
+  // a link's parking queue moved on in the front pass: fetch its new head
+  // record now, store it at the end
+  const bool refill = act && lmeta_k((uint32_t)info.y) == 0 && qrec.x < 0 &&
+                      qhead < info.w;
+  v4i nrec = {-1, 0, 0, 0};
+  if (refill) nrec = wait_rec[qhead];
   if (act) {
     hp = sum.z;
-    cnt = sum.w;
+    cnt = hc_cnt(sum.z);
     const uint32_t meta = (uint32_t)info.y;
     len = lmeta_len(meta);
     s_base[i] = info.x;
@@ -626,15 +628,16 @@ __global__ __launch_bounds__(kWave) void k_back(
   wave_lds_sync();
   if (act) {
     int4 e = s_ends[i];
+    int hc = hc_make(hc_head(hp), hc_par(hp), cnt);
     if (s_left[i]) {
-      const int h = wrapi(hp_head(hp) + 1, len);
-      lane_hc[gid] = (v2i){(hp & ~0xFFFF) | h, cnt - 1};
+      hc = hc_make(wrapi(hc_head(hp) + 1, len), hc_par(hp), cnt - 1);
       const int2 sec = s_second[i];
       e.x = sec.x;  // the vehicle behind is the new lead
       e.y = sec.y;
     }
-    lane_ends[gid] = (v4i){e.x, e.y, e.z, e.w};
+    lane_state[gid] = (v4i){e.x, e.y, e.z, hc};
   }
+  if (refill) lane_qrec[gid] = nrec;
   sumv = wave_sum(sumv);
   cross = wave_sum(cross);
   exits = wave_sum(exits);
@@ -758,29 +761,32 @@ __global__ void k_stats(const DevScen* d, unsigned long long* out, int ring) {
     }
   } else {
     // move-tile counters: one per lane at most (balanced tiles included)
-    const long long n1 = S.n_veh, n2 = n1 + S.n_links, n3 = n2 + S.n_lanes,
+    const long long n1 = S.n_veh, n2 = n1 + S.n_lanes, n3 = n2 + S.n_lanes,
                     n4 = n3 + S.n_lanes, n5 = n4 + S.n_ftiles;
     for (long long g = g0; g < n5; g += stride) {
       if (g < n1) {
         h += veh_hash((int)g, kArrived, 0, 0, 0, 0, 0);
       } else if (g < n2) {
-        const int link = (int)(g - n1);
-        for (int q = S.wait_head[link]; q < S.wait_off[link + 1]; ++q) {
-          const int id = S.wait_rec[q].x;
-          h += veh_hash(id, kWaiting, 0, 0, 0, 0, 0) -
-               veh_hash(id, kArrived, 0, 0, 0, 0, 0);
-          ++wait;
-        }
+        // lane k == 0 of a link holds the link's parking queue
+        const int gid = (int)(g - n1);
+        const int4 info = S.lane_info[gid];
+        if (lmeta_k((uint32_t)info.y) == 0)
+          for (int q = S.lane_qhead[gid]; q < info.w; ++q) {
+            const int id = S.wait_rec[q].x;
+            h += veh_hash(id, kWaiting, 0, 0, 0, 0, 0) -
+                 veh_hash(id, kArrived, 0, 0, 0, 0, 0);
+            ++wait;
+          }
       } else if (g < n3) {
         const int gid = (int)(g - n2);
-        const int2 hc = S.lane_hc[gid];
         const int4 info = S.lane_info[gid];
+        const int hc = S.lane_state[gid].w;
         const int link = info.z;
         const int k = lmeta_k((uint32_t)info.y);
         const int len = lmeta_len((uint32_t)info.y);
         const int base = info.x;
-        for (int j = 0; j < hc.y; ++j) {
-          const int slot = rec_slot(base, hc.x, len, j);
+        for (int j = 0; j < hc_cnt(hc); ++j) {
+          const int slot = rec_slot(base, hc, len, j);
           const uint2 hw = S.hot[slot];
           const int id = (int)hw.y;
           const int rptr = (int)(S.cold[slot].x - S.route_off[id]);
@@ -788,7 +794,7 @@ __global__ void k_stats(const DevScen* d, unsigned long long* out, int ring) {
                         xvf_v(hw.x), rptr) -
                veh_hash(id, kArrived, 0, 0, 0, 0, 0);
         }
-        act += hc.y;
+        act += hc_cnt(hc);
         // a vehicle handed over in the last step is on this lane already
         const int4 ha = S.hand_a[gid];
         if (ha.x == S.t - 1) {
@@ -837,19 +843,21 @@ __global__ void k_export_set(const DevScen* d, ExportBufs o, int ring) {
     o.v[id] = (int8_t)S.ring_v[g];
     return;
   }
-  if (g < S.n_links) {
-    for (int q = S.wait_head[g]; q < S.wait_off[g + 1]; ++q)
-      o.status[S.wait_rec[q].x] = kWaiting;
-  } else if (g < S.n_links + S.n_lanes) {
-    const int gid = g - S.n_links;
-    const int2 hc = S.lane_hc[gid];
+  if (g < S.n_lanes) {
+    const int4 info = S.lane_info[g];
+    if (lmeta_k((uint32_t)info.y) == 0)
+      for (int q = S.lane_qhead[g]; q < info.w; ++q)
+        o.status[S.wait_rec[q].x] = kWaiting;
+  } else if (g < 2 * S.n_lanes) {
+    const int gid = g - S.n_lanes;
+    const int hc = S.lane_state[gid].w;
     const int4 info = S.lane_info[gid];
     const int link = info.z;
     const int k = lmeta_k((uint32_t)info.y);
     const int len = lmeta_len((uint32_t)info.y);
     const int base = info.x;
-    for (int j = 0; j < hc.y; ++j) {
-      const int slot = rec_slot(base, hc.x, len, j);
+    for (int j = 0; j < hc_cnt(hc); ++j) {
+      const int slot = rec_slot(base, hc, len, j);
       const uint2 hw = S.hot[slot];
       const int id = (int)hw.y;
       o.status[id] = kActive;
@@ -946,7 +954,7 @@ hipError_t launch_export(const DevScen* d_desc, ExportBufs out, int n_veh,
   if (n_veh > 0)
     hipLaunchKernelGGL(k_export_fill, dim3((n_veh + 255) / 256), dim3(256), 0,
                        s, out, n_veh);
-  const int n = ring ? n_veh : n_links + n_lanes;
+  const int n = ring ? n_veh : 2 * n_lanes;
   if (n > 0)
     hipLaunchKernelGGL(k_export_set, dim3((n + 255) / 256), dim3(256), 0, s,
                        d_desc, out, ring);

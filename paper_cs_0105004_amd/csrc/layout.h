@@ -57,6 +57,18 @@ __host__ __device__ inline uint32_t rinfo_flags(uint32_t r) {
   return ((r >> 30) & 1u) | (((r >> 26) & 3u) << 1) | (((r >> 28) & 3u) << 3);
 }
 
+// a lane's queue: head index (bits 0-14), buffer parity (15), count (16-31)
+__host__ __device__ inline int hc_make(int head, int par, int cnt) {
+  return head | (par << 15) | (cnt << 16);
+}
+__host__ __device__ inline int hc_head(int h) { return h & 0x7FFF; }
+__host__ __device__ inline int hc_par(int h) { return (h >> 15) & 1; }
+__host__ __device__ inline int hc_cnt(int h) { return (int)((uint32_t)h >> 16); }
+
+// a waiting vehicle: {id, depart | flags on its first link << 27, rp of its
+// first route entry, route info of its second entry (0 if none)}
+constexpr int kDepartBits = 27;
+
 // static per-lane word: len (bits 0-14), lane index k (15-16), lanes-1
 // (17-18), rank of the link at its downstream node (19-25)
 __host__ __device__ inline uint32_t lmeta_make(int len, int k, int lanes,
@@ -95,7 +107,7 @@ enum : int {
 // modifies it:
 //   x = target lane id of the lead vehicle (-1: not near the node, -2: trip
 //       ends at the node), y = x of the rearmost vehicle (len if empty),
-//   z = head|parity and w = count of the lane's queue as the move finds it
+//   z = the lane's queue (hc) as the move finds it
 
 struct DevScen {
   uint32_t flags;
@@ -111,14 +123,18 @@ struct DevScen {
   int64_t n_route;
   // links, in the library's internal (tile) order
   const int32_t* link_ext;    // caller's link id
-  // lanes: {record base, lmeta, link, lane id of the link's lane 0}
+  // lanes: {record base, lmeta, link, end of the link's parking queue}
   const int4* lane_info;
-  int2* lane_hc;             // {head | parity << 16, count}
-  int4* lane_ends;           // after the move: {lead xvf, lead ninfo, rear xvf}
-  int4* lane_sum;            // {target, rear x, head|parity, count}
+  int4* lane_state;          // {lead xvf, lead ninfo, rear xvf, hc} after
+                             // the move sub-step
+  int4* lane_sum;            // {target, rear x, hc, 0} after sub-step 1
   int32_t* claim;            // smallest (rank, lane) key aiming at the lane
   int4* hand_a;              // arrival handoff {tag = t, xvf, id, rp}
   int32_t* hand_b;           // arrival handoff: ninfo
+  // parking queue of a link, kept with its lane 0: the index of its head in
+  // wait_rec and a copy of that record (id -1: to be fetched again)
+  int32_t* lane_qhead;
+  int4* lane_qrec;
   // vehicle records
   uint2* hot;
   int2* cold;
@@ -134,12 +150,8 @@ struct DevScen {
   int4* xlist;
   int32_t* xcount;
   int32_t xcap;  // entries of xlist (0: every tile is one run)
-  // parking queues per link, ordered by (depart, id):
-  // wait_rec = {id, depart, rp of the first entry, ninfo of the second}
-  const int32_t* wait_off;
+  // parking queues, link by link, each ordered by (depart, id)
   const int4* wait_rec;
-  const int32_t* wait_info0;  // route info of the first entry
-  int32_t* wait_head;
   // routes
   const int64_t* route_off;
   const uint32_t* route_info;

@@ -33,6 +33,7 @@ struct Slot {
   int64_t n_route = 0, n_records = 0, n_cells = 0;
   std::vector<int32_t> ext_of, int_of;  // internal <-> caller link ids
   std::vector<int32_t> len, lanes, lane0, from, to, base;  // internal order
+  std::vector<int4> lane_info;
   std::vector<int32_t> conn_off, conn_out;  // internal ids (turn lanes)
   std::vector<int8_t> conn_lo, conn_hi;
   std::vector<int2> tiles, ftiles;  // move sub-step / lane-change sub-step
@@ -126,28 +127,26 @@ void carve_network(Carve& cv, const NetDims& nd, DevScen& d, bool ring) {
   const int64_t L = nd.L, Q = nd.Q;
   d.link_ext = cv.take<int32_t>(L);
   d.lane_info = cv.take<int4>(Q);
-  d.lane_hc = cv.take<int2>(Q);
+  d.lane_state = cv.take<int4>(Q);
   d.lane_sum = cv.take<int4>(Q);
   d.claim = cv.take<int32_t>(Q);
   d.hand_a = cv.take<int4>(Q);
   d.hand_b = cv.take<int32_t>(Q);
+  d.lane_qhead = cv.take<int32_t>(Q);
+  d.lane_qrec = cv.take<int4>(Q);
   d.hot = cv.take<uint2>(ring ? 0 : nd.rec);
   d.cold = cv.take<int2>(ring ? 0 : nd.rec);
-  d.lane_ends = cv.take<int4>(Q);
   d.tile_ctr = cv.take<long long>(Q * C_N);  // at most one tile per lane
   d.ftile_ctr = cv.take<long long>(Q * C_N);
   d.tile_np = cv.take<int32_t>(Q);  // at most one tile per lane
   d.xlist = cv.take<int4>(nd.xcap);
   d.xcount = cv.take<int32_t>(2);
-  d.wait_off = cv.take<int32_t>(L + 1);
-  d.wait_head = cv.take<int32_t>(L);
   d.ring_ctr = cv.take<long long>(C_N);
   d.err = cv.take<uint32_t>(1);
 }
 
 void carve_vehicles(Carve& cv, int64_t n, int64_t R, DevScen& d, bool ring) {
   d.wait_rec = cv.take<int4>(ring ? 0 : n);
-  d.wait_info0 = cv.take<int32_t>(ring ? 0 : n);
   d.route_off = cv.take<int64_t>(ring ? 0 : n + 1);
   d.route_info = cv.take<uint32_t>(R);
   d.exit_t = cv.take<int32_t>(R);
@@ -397,7 +396,8 @@ extern "C" sim_status sim_load_network(sim_ctx* c, int32_t slot,
       S.conn_off[i + 1] = (int32_t)S.conn_out.size();
     }
   }
-  std::vector<int4> lane_info(S.n_lanes);
+  std::vector<int4>& lane_info = S.lane_info;
+  lane_info.assign(S.n_lanes, make_int4(0, 0, 0, 0));
   S.base.resize(L);
   int64_t rec = 0;
   for (int32_t i = 0; i < L; ++i) {
@@ -458,6 +458,7 @@ extern "C" sim_status sim_load_vehicles(sim_ctx* c, int32_t slot,
   const int32_t n = v->n;
   const int vmax = S.p.vmax;
   if (n > 0 && !v->depart) return fail(c, SIM_E_INVAL, "depart is NULL");
+  if (v->t0 < 0) return fail(c, SIM_E_INVAL, "t0 must be >= 0");
   const bool has_init = v->init_status != nullptr;
   if (has_init && (!v->init_lane || !v->init_x || !v->init_v ||
                    (!S.ring && !v->init_rptr)))
@@ -468,10 +469,9 @@ extern "C" sim_status sim_load_vehicles(sim_ctx* c, int32_t slot,
   {
     std::vector<int4> hand_a(S.n_lanes, make_int4(kTagNone, 0, 0, 0));
     HIPCHK(c, up(d.hand_a, hand_a.data(), S.n_lanes, s));
-    HIPCHK(c, hipMemsetAsync(d.lane_hc, 0, sizeof(int2) * S.n_lanes, s));
+    HIPCHK(c, hipMemsetAsync(d.lane_state, 0, sizeof(int4) * S.n_lanes, s));
     HIPCHK(c, hipMemsetAsync(d.tile_ctr, 0, sizeof(long long) * C_N * S.n_lanes, s));
     HIPCHK(c, hipMemsetAsync(d.ftile_ctr, 0, sizeof(long long) * C_N * S.n_ftiles, s));
-    HIPCHK(c, hipMemsetAsync(d.lane_ends, 0, sizeof(int4) * S.n_lanes, s));
     HIPCHK(c, hipMemsetAsync(d.xcount, 0, sizeof(int32_t) * 2, s));
     HIPCHK(c, hipMemsetAsync(d.tile_np, 0, sizeof(int32_t) * S.n_lanes, s));
     HIPCHK(c, hipMemsetAsync(d.ring_ctr, 0, sizeof(long long) * C_N, s));
@@ -588,8 +588,7 @@ extern "C" sim_status sim_load_vehicles(sim_ctx* c, int32_t slot,
       if (qa != qb) return qa < qb;
       return v->init_x[a] > v->init_x[b];
     });
-    std::vector<int2> hc(S.n_lanes, make_int2(0, 0));
-    std::vector<int4> ends(S.n_lanes, make_int4(0, 0, 0, 0));
+    std::vector<int4> state(S.n_lanes, make_int4(0, 0, 0, 0));
     // records of each lane's run are contiguous from the lane's base
     std::vector<uint2> hot;
     std::vector<int2> cold;
@@ -613,9 +612,8 @@ extern "C" sim_status sim_load_vehicles(sim_ctx* c, int32_t slot,
                                  (uint32_t)i));
         cold.push_back(make_int2((int32_t)rp, ninfo_of(rp, i)));
       }
-      hc[qq] = make_int2(0, (int32_t)(b - a));
-      ends[qq] = make_int4((int)hot[run_first.back()].x, cold[run_first.back()].y,
-                           (int)hot.back().x, 0);
+      state[qq] = make_int4((int)hot[run_first.back()].x, cold[run_first.back()].y,
+                            (int)hot.back().x, hc_make(0, 0, (int)(b - a)));
       a = b;
     }
     // parking queues ordered by (depart, id)
@@ -633,12 +631,23 @@ extern "C" sim_status sim_load_vehicles(sim_ctx* c, int32_t slot,
                   });
     }
     std::vector<int4> wrec(wid.size());
-    std::vector<int32_t> winfo0(wid.size());
     for (size_t j = 0; j < wid.size(); ++j) {
       const int32_t i = wid[j];
       const int64_t r0 = v->route_off[i];
-      wrec[j] = make_int4(i, v->depart[i], (int32_t)r0, ninfo_of(r0, i));
-      winfo0[j] = (int32_t)rinfo[r0];
+      if (v->depart[i] < 0 || v->depart[i] >= (1 << kDepartBits))
+        return fail(c, SIM_E_INVAL, "vehicle %d: depart must be 0..2^%d-1", i, kDepartBits);
+      wrec[j] = make_int4(i, v->depart[i] | (int)(rinfo_flags(rinfo[r0]) << kDepartBits),
+                          (int32_t)r0, ninfo_of(r0, i));
+    }
+    // each link's queue is kept with its lane 0: head index and head record;
+    // every lane of the link knows where the queue ends
+    std::vector<int32_t> qhead(S.n_lanes, 0);
+    std::vector<int4> qrec(S.n_lanes, make_int4(-1, 0, 0, 0));
+    for (int32_t l = 0; l < L; ++l) {
+      const int32_t q0 = S.lane0[l];
+      qhead[q0] = wait_cnt[l];
+      if (wait_cnt[l] < wait_cnt[l + 1]) qrec[q0] = wrec[wait_cnt[l]];
+      for (int k = 0; k < S.lanes[l]; ++k) S.lane_info[q0 + k].w = wait_cnt[l + 1];
     }
     std::vector<int32_t> exit_t(R, -1);
     if (v->exit_t0) std::copy(v->exit_t0, v->exit_t0 + R, exit_t.begin());
@@ -652,9 +661,9 @@ extern "C" sim_status sim_load_vehicles(sim_ctx* c, int32_t slot,
     d.n_route = R;
     d.t = v->t0;
     HIPCHK(c, up(const_cast<int4*>(d.wait_rec), wrec.data(), (int64_t)wrec.size(), s));
-    HIPCHK(c, up(const_cast<int32_t*>(d.wait_info0), winfo0.data(), (int64_t)winfo0.size(), s));
-    HIPCHK(c, up(const_cast<int32_t*>(d.wait_off), wait_cnt.data(), L + 1, s));
-    HIPCHK(c, up(d.wait_head, wait_cnt.data(), L, s));
+    HIPCHK(c, up(d.lane_qhead, qhead.data(), S.n_lanes, s));
+    HIPCHK(c, up(d.lane_qrec, qrec.data(), S.n_lanes, s));
+    HIPCHK(c, up(const_cast<int4*>(d.lane_info), S.lane_info.data(), S.n_lanes, s));
     HIPCHK(c, up(const_cast<int64_t*>(d.route_off), v->route_off, n + 1, s));
     HIPCHK(c, up(const_cast<uint32_t*>(d.route_info), rinfo.data(), R, s));
     HIPCHK(c, up(d.exit_t, exit_t.data(), R, s));
@@ -662,8 +671,7 @@ extern "C" sim_status sim_load_vehicles(sim_ctx* c, int32_t slot,
       HIPCHK(c, up(d.hot + run_slot[r], hot.data() + run_first[r], run_len[r], s));
       HIPCHK(c, up(d.cold + run_slot[r], cold.data() + run_first[r], run_len[r], s));
     }
-    HIPCHK(c, up(d.lane_hc, hc.data(), S.n_lanes, s));
-    HIPCHK(c, up(d.lane_ends, ends.data(), S.n_lanes, s));
+    HIPCHK(c, up(d.lane_state, state.data(), S.n_lanes, s));
     HIPCHK(c, hipStreamSynchronize(s));
     S.n_route = R;
   }
