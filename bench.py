@@ -52,16 +52,57 @@ def make_workload(name: str, steps: int):
     return scen, cfg
 
 
-# algorithmic bytes of one launch of each step kernel, per unit
-#   back  (move sub-step): per vehicle 12 B (read xvf+id, write xvf), per lane
-#         16 B (header + summary), per node passage 32 B (read route state,
-#         write exit time, write the 20-byte handoff)
-#   front (lane-change sub-step): per lane 40 B (header r/w, handoff slot
-#         read, summary write), per vehicle placed (arrival or parking) 24 B
-def algorithmic_bytes(kind, n_veh, n_lanes, n_pass, n_placed):
+# Algorithmic bytes of the method per step (the lattice formulation: every
+# cell of an occupied lane read and written once as int8, each active
+# vehicle's int32 id read and written, 16 B per crossing or trip end for its
+# route entry, exit time and handoff record, 8 B per vehicle leaving parking):
+#   B(t) = 2*C_occ(t) + 8*N(t) + 16*X(t) + 8*I(t)
+# The move kernel does the first three terms, the front kernel the last.
+def algorithmic_bytes(kind, st):
     if kind == "back":
-        return 12.0 * n_veh + 16.0 * n_lanes + 32.0 * n_pass
-    return 40.0 * n_lanes + 24.0 * n_placed
+        return (2.0 * st["c_occ"] + 8.0 * st["veh_updates"]
+                + 16.0 * (st["crossings"] + st["exits"]))
+    if kind == "front":
+        return 8.0 * st["insertions"]
+    return 2.0 * st["c_occ"] + 8.0 * st["veh_updates"]  # ring: one launch
+
+
+KERNEL_SOURCES = ("kernels.hip", "kernels.h", "layout.h", "philox.h")
+
+
+def kernel_digest() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_cs_0105004_amd", "csrc", f),
+                  "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+# HBM bytes per launch of the move kernel on the default workload, from
+# rocprofv3 FETCH_SIZE and WRITE_SIZE (KiB per dispatch, mean over the run)
+# scaled by what the same counters read for a plain copy of known size.
+# Valid only for the kernel sources with this digest.
+MEASURED_TRAFFIC = {
+    # FETCH 2860.0 KiB x 2.0 + WRITE 2284.9 KiB x 1.0 per dispatch
+    "3de1834b6ced0b63": {"kernel": "back", "steps": 3600,
+                         "bytes_per_launch": 8004.3 * 1024},
+}
+
+
+def copy_calibration(nbytes: int, reps: int = 5):
+    """Plain device-to-device copies of nbytes bytes, for calibrating the
+    memory counters (run under rocprofv3 --pmc)."""
+    import torch
+    a = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1)
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": nbytes, "reps": reps}), flush=True)
+    return 0
 
 
 def cpu_baseline(scen, budget_s: float):
@@ -93,6 +134,11 @@ def main():
     ap.add_argument("--tile-lanes", type=int, default=0)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--reps", type=int, default=5,
+                    help="further runs of K steps for the run-latency "
+                         "percentiles")
+    ap.add_argument("--copy-calibration", type=int, default=0,
+                    metavar="BYTES", help="only run plain copies of BYTES")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not "
@@ -104,6 +150,8 @@ def main():
     from paper_cs_0105004_amd.sim import Context
 
     torch.cuda.set_device(0)
+    if args.copy_calibration > 0:
+        return copy_calibration(args.copy_calibration)
     log(f"bench: generating workload {args.workload}")
     scen, cfg = make_workload(args.workload, args.steps)
     ctx = Context(max_slots=2, tile_lanes=args.tile_lanes)
@@ -124,8 +172,19 @@ def main():
     st = ctx.stats(0)
     value = st["veh_updates"] / wall
 
-    # kernel timing pass: the same K steps again, each launch bracketed by
-    # HIP events on the library's stream
+    # run latency: the same K-step run from a fresh load, several times
+    runs = [wall]
+    for _ in range(max(args.reps, 0)):
+        ctx.load(0, scen)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        ctx.step(0, args.steps)
+        torch.cuda.synchronize()
+        runs.append(time.perf_counter() - t1)
+        assert ctx.stats(0)["hash"] == st["hash"], "repeat run diverged"
+
+    # kernel timing pass: the same K steps again, inside HIP graphs with an
+    # event between every two kernels on the library's stream
     ctx.load(0, scen)
     ctx.profile(True)
     ctx.step(0, args.steps)
@@ -135,27 +194,32 @@ def main():
     assert st2["hash"] == st["hash"], "timing pass diverged"
     tiling = ctx.tiling(0)
     K = max(args.steps, 1)
-    per = {"veh": st["veh_updates"] / K, "lanes": tiling["n_lanes"],
-           "pass": (st["crossings"] + st["exits"]) / K,
-           "placed": (st["insertions"] + st["crossings"]) / K}
     roof = None
     kinds = [k for k in ("front", "back", "ring") if kt[k][0] > 0]
     if kinds:
         dom = max(kinds, key=lambda k: kt[k][1])
-        avg_ms = kt[dom][1] / kt[dom][0]
-        if dom == "ring":
-            bytes_launch = 12.0 * st["veh_updates"]  # one launch, all steps
-        else:
-            bytes_launch = algorithmic_bytes(dom, per["veh"], per["lanes"],
-                                             per["pass"], per["placed"])
+        launches = kt[dom][0]
+        avg_ms = kt[dom][1] / launches
+        bytes_launch = algorithmic_bytes(dom, st) / launches
         achieved = bytes_launch / (avg_ms * 1e-3) / 1e9
-        roof = {"bound": "hbm", "kernel": f"k_{dom}", "achieved": achieved,
+        digest = kernel_digest()
+        traffic = None
+        tr = MEASURED_TRAFFIC.get(digest)
+        if tr is not None and args.workload == "portland" and \
+                args.steps == tr["steps"] and dom == tr["kernel"]:
+            traffic = tr["bytes_per_launch"]
+        roof = {"bound": "hbm", "achieved": achieved,
                 "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                "avg_launch_us": avg_ms * 1e3,
-                "bytes_per_launch": bytes_launch,
+                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                "kernel": f"k_{dom}", "avg_launch_us": avg_ms * 1e3,
+                "algorithmic_bytes_per_launch": bytes_launch,
+                "kernel_sources_digest": digest,
                 "kernel_ms": {k: kt[k][1] for k in kinds},
                 "launches": {k: kt[k][0] for k in kinds}}
+    srt = sorted(runs)
+
+    def pct(q):
+        return srt[min(len(srt) - 1, int(round(q * (len(srt) - 1))))] * 1e3
     out = {
         "metric": METRIC, "value": value, "unit": "vehicle-updates/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -165,6 +229,8 @@ def main():
         "sim_real_time_ratio": args.steps / wall,
         "vehicle_updates": st["veh_updates"], "wall_s": wall,
         "bit_exact_state_hash": f"{st['hash']:016x}",
+        "run_latency_ms": {"p50": pct(0.5), "p99": pct(0.99),
+                           "runs": len(runs)},
         "tiling": {"tiles": tiling["n_tiles"], "e_dmn": tiling["e_dmn"],
                    "e_tile": tiling["e_tile"]},
         "roofline": roof,

@@ -203,11 +203,17 @@ typedef struct {
 
 sim_status sim_tiling_info(const sim_ctx* ctx, int32_t slot, sim_tiling* out);
 
-/* Kernel timing (the paper monitors the time per step): while enabled,
-   sim_step brackets every kernel launch with HIP events on the context
-   stream.  sim_kernel_times waits for the stream, reports per kernel kind
-   (0 = front/lane-change sub-step, 1 = back/move sub-step, 2 = ring) the
-   number of launches and their summed duration, and resets the sums. */
+/* Kernel timing (the paper monitors the time per step, Section "Adaptive
+   Load Balancing"): while enabled, sim_step runs its steps as HIP graphs
+   with an event node before the first kernel and after every kernel, and
+   with eight back-to-back event nodes ahead of them; a kernel's time is the
+   interval between the events around it less the mean interval between two
+   back-to-back events of the same replay (the cost of an event node
+   itself).  With graph_steps < 0, and for the ring kernel, each launch is
+   bracketed by two events on the context stream instead (no correction).
+   sim_kernel_times waits for the stream, reports per kernel kind (0 = front
+   / lane-change sub-step, 1 = back / move sub-step, 2 = ring) the number of
+   launches and their summed duration, and resets the sums. */
 typedef struct {
   int64_t launches;
   double total_ms;

@@ -68,9 +68,15 @@ struct sim_ctx {
   int graph_k = 0;
   // kernel timing
   bool profile = false;
-  std::vector<hipEvent_t> events;  // pairs around launches
+  std::vector<hipEvent_t> events;  // pairs around direct launches
   std::vector<int> event_kind;     // kind of each pair
   size_t n_pairs = 0;
+  // profiled graphs: an event before the first kernel and after each one
+  hipGraphExec_t pgraph = nullptr;
+  int pgraph_k = 0;
+  std::vector<hipEvent_t> gev;
+  int64_t acc_launches[3] = {0, 0, 0};
+  double acc_ms[3] = {0, 0, 0};
   std::string err;
 };
 
@@ -283,6 +289,8 @@ extern "C" sim_status sim_destroy(sim_ctx* c) {
   if (!c) return SIM_E_INVAL;
   if (c->stream || c->d_descs) (void)hipStreamSynchronize(c->stream);
   for (hipEvent_t e : c->events) (void)hipEventDestroy(e);
+  for (hipEvent_t e : c->gev) (void)hipEventDestroy(e);
+  if (c->pgraph) (void)hipGraphExecDestroy(c->pgraph);
   if (c->d_descs) (void)hipFree(c->d_descs);
   if (c->d_stats) (void)hipFree(c->d_stats);
   if (c->d_work) (void)hipFree(c->d_work);
@@ -715,6 +723,11 @@ sim_status build_work(sim_ctx* c, const std::vector<int32_t>& net,
     c->graph = nullptr;
     c->graph_k = 0;
   }
+  if (c->pgraph) {
+    (void)hipGraphExecDestroy(c->pgraph);
+    c->pgraph = nullptr;
+    c->pgraph_k = 0;
+  }
   if (work.size() > c->work_cap) {
     if (c->d_work) HIPCHK(c, hipFree(c->d_work));
     c->d_work = nullptr;
@@ -742,8 +755,20 @@ sim_status build_work(sim_ctx* c, const std::vector<int32_t>& net,
 
 // A HIP graph of K steps of the current work list (two kernels per step) and
 // the advance of t by K, built node by node (the caller's stream may be the
-// legacy default stream, which cannot be captured).
-sim_status build_graph(sim_ctx* c, int K) {
+// legacy default stream, which cannot be captured).  A profiled graph also
+// records kLeadEvents events back to back, the last of them just before the
+// first kernel, and one event after every kernel, so that consecutive events
+// bracket one kernel each with no host gap in between.
+constexpr int kLeadEvents = 8;  // back-to-back events that time an event
+
+sim_status build_graph(sim_ctx* c, int K, bool profiled, hipGraphExec_t* out) {
+  if (profiled) {
+    while (c->gev.size() < (size_t)(2 * K + kLeadEvents)) {
+      hipEvent_t ev;
+      HIPCHK(c, hipEventCreate(&ev));
+      c->gev.push_back(ev);
+    }
+  }
   hipGraph_t g = nullptr;
   HIPCHK(c, hipGraphCreate(&g, 0));
   const bool batched = c->single_slot < 0;
@@ -754,6 +779,14 @@ sim_status build_graph(sim_ctx* c, int K) {
   const int4* work = c->d_work;
   hipGraphNode_t prev = nullptr;
   hipError_t e = hipSuccess;
+  int n_ev = 0;
+  auto mark = [&]() {
+    if (e != hipSuccess || !profiled) return;
+    hipGraphNode_t node;
+    e = hipGraphAddEventRecordNode(&node, g, prev ? &prev : nullptr, prev ? 1 : 0,
+                                   c->gev[n_ev++]);
+    prev = node;
+  };
   auto add = [&](void* fn, int grid, int block, size_t shmem, void** args) {
     if (e != hipSuccess) return;
     hipKernelNodeParams kp{};
@@ -767,13 +800,16 @@ sim_status build_graph(sim_ctx* c, int K) {
     e = hipGraphAddKernelNode(&node, g, prev ? &prev : nullptr, prev ? 1 : 0, &kp);
     prev = node;
   };
+  for (int j = 0; j < kLeadEvents; ++j) mark();
   for (int s = 0; s < K; ++s) {
     int step = s;
     void* fa[] = {&descs, &slot, &work, &pieces, &step};
     add(front_kernel(batched), c->n_work, kFrontThreads, (size_t)3 * c->lc_cells, fa);
+    mark();
     void* ba[] = {&descs, &slot, &work, &n_work, &step};
     add(back_kernel(batched), c->n_work + (batched ? 0 : c->n_extra),
         kBackThreadsPerPiece, 0, ba);
+    mark();
   }
   DevScen* mdescs = c->d_descs;
   const int* list = c->d_list;
@@ -784,9 +820,28 @@ sim_status build_graph(sim_ctx* c, int K) {
   if (e == hipSuccess) e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
   (void)hipGraphDestroy(g);
   if (e != hipSuccess) return fail(c, SIM_E_DEVICE, "graph: %s", hipGetErrorString(e));
-  if (c->graph) (void)hipGraphExecDestroy(c->graph);
-  c->graph = ex;
-  c->graph_k = K;
+  *out = ex;
+  return SIM_OK;
+}
+
+// Replays a profiled graph of K steps once and adds its per-kernel times.
+sim_status run_profiled(sim_ctx* c, hipGraphExec_t ex, int K) {
+  HIPCHK(c, hipGraphLaunch(ex, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  double ev = 0;  // mean cost of one event node
+  for (int j = 0; j + 1 < kLeadEvents; ++j) {
+    float ms = 0;
+    HIPCHK(c, hipEventElapsedTime(&ms, c->gev[j], c->gev[j + 1]));
+    ev += ms;
+  }
+  ev /= (kLeadEvents - 1);
+  const int e0 = kLeadEvents - 1;  // the event before the first kernel
+  for (int j = 0; j < 2 * K; ++j) {
+    float ms = 0;
+    HIPCHK(c, hipEventElapsedTime(&ms, c->gev[e0 + j], c->gev[e0 + j + 1]));
+    c->acc_launches[j & 1]++;
+    c->acc_ms[j & 1] += std::max(0.0, (double)ms - ev);
+  }
   return SIM_OK;
 }
 
@@ -825,14 +880,18 @@ extern "C" sim_status sim_kernel_times(sim_ctx* c, sim_kernel_time out[3]) {
   if (!c) return SIM_E_INVAL;
   if (!out) return fail(c, SIM_E_INVAL, "out is NULL");
   HIPCHK(c, hipStreamSynchronize(c->stream));
-  for (int k = 0; k < 3; ++k) out[k] = sim_kernel_time{0, 0.0};
   for (size_t p = 0; p < c->n_pairs; ++p) {
     float ms = 0;
     HIPCHK(c, hipEventElapsedTime(&ms, c->events[2 * p], c->events[2 * p + 1]));
-    out[c->event_kind[p]].launches++;
-    out[c->event_kind[p]].total_ms += ms;
+    c->acc_launches[c->event_kind[p]]++;
+    c->acc_ms[c->event_kind[p]] += ms;
   }
   c->n_pairs = 0;
+  for (int k = 0; k < 3; ++k) {
+    out[k] = sim_kernel_time{c->acc_launches[k], c->acc_ms[k]};
+    c->acc_launches[k] = 0;
+    c->acc_ms[k] = 0;
+  }
   return SIM_OK;
 }
 
@@ -859,10 +918,36 @@ extern "C" sim_status sim_step(sim_ctx* c, const int32_t* slots, int32_t n_slots
   if (!net.empty()) {
     const int K = c->cfg.graph_steps;
     int32_t done = 0;
-    if (K > 0 && !c->profile && n_steps >= K) {
-      if (!c->graph || c->graph_k != K) {
-        st = build_graph(c, K);
+    if (K > 0 && c->profile) {
+      // profiled: graphs with events between the kernels, harvested after
+      // every replay (the remainder gets a graph of its own)
+      if (n_steps >= K && (!c->pgraph || c->pgraph_k != K)) {
+        if (c->pgraph) (void)hipGraphExecDestroy(c->pgraph);
+        c->pgraph = nullptr;
+        st = build_graph(c, K, true, &c->pgraph);
         if (st != SIM_OK) return st;
+        c->pgraph_k = K;
+      }
+      for (; done + K <= n_steps; done += K) {
+        st = run_profiled(c, c->pgraph, K);
+        if (st != SIM_OK) return st;
+      }
+      if (done < n_steps) {
+        hipGraphExec_t rg = nullptr;
+        st = build_graph(c, n_steps - done, true, &rg);
+        if (st != SIM_OK) return st;
+        st = run_profiled(c, rg, n_steps - done);
+        (void)hipGraphExecDestroy(rg);
+        if (st != SIM_OK) return st;
+        done = n_steps;
+      }
+    } else if (K > 0 && n_steps >= K) {
+      if (!c->graph || c->graph_k != K) {
+        if (c->graph) (void)hipGraphExecDestroy(c->graph);
+        c->graph = nullptr;
+        st = build_graph(c, K, false, &c->graph);
+        if (st != SIM_OK) return st;
+        c->graph_k = K;
       }
       for (; done + K <= n_steps; done += K) HIPCHK(c, hipGraphLaunch(c->graph, c->stream));
     }

@@ -269,54 +269,82 @@ def grid_network(rows: int, cols: int, n_links: int, rng: np.random.Generator,
     return frm, to, length, lanes, xy
 
 
-def shortest_routes(n_nodes, frm, to, length, orig, dest, chunk=512):
+def shortest_routes(n_nodes, frm, to, length, orig, dest, chunk=512,
+                    max_veh_chunk=200_000):
     """Shortest routes by length (scipy Dijkstra) from orig[i] to dest[i].
-    Returns (route_off int64, route_links int32)."""
+    Sources are taken `chunk` at a time, fewer when their vehicles exceed
+    max_veh_chunk.  Returns (route_off int64, route_links int32)."""
     from scipy.sparse import csr_matrix
     from scipy.sparse.csgraph import dijkstra
     L = len(frm)
     w = csr_matrix((length.astype(np.float64), (frm, to)),
                    shape=(n_nodes, n_nodes))
-    lid = csr_matrix((np.arange(L, dtype=np.float64) + 1, (frm, to)),
-                     shape=(n_nodes, n_nodes))
-    lid_dense_rows = lid.tocsr()
+    # link id of a (from, to) pair: the out-links of every node, padded
+    outdeg = np.bincount(frm, minlength=n_nodes)
+    D = max(1, int(outdeg.max()) if L else 1)
+    by_from = np.argsort(frm, kind="stable")
+    first = np.zeros(n_nodes + 1, np.int64)
+    np.cumsum(outdeg, out=first[1:])
+    slot = np.arange(L) - first[frm[by_from]]
+    adj_link = np.full((n_nodes, D), -1, np.int64)
+    adj_link[frm[by_from], slot] = by_from
+    adj_to = np.full((n_nodes, D), -1, np.int64)
+    adj_to[frm[by_from], slot] = to[by_from]
     n = len(orig)
-    paths = [None] * n
+    orig = np.asarray(orig, np.int64)
+    dest = np.asarray(dest, np.int64)
     uniq = np.unique(orig)
     order = np.argsort(orig, kind="stable")
     sorted_orig = orig[order]
-    for c0 in range(0, len(uniq), chunk):
-        srcs = uniq[c0:c0 + chunk]
+    lens = np.zeros(n, np.int64)
+    pieces = []  # (vehicle ids, their links back to front, lengths)
+    per_src = np.diff(np.searchsorted(sorted_orig,
+                                      np.append(uniq, uniq[-1] + 1)
+                                      if len(uniq) else uniq))
+    bounds = [0]
+    while bounds[-1] < len(uniq):
+        b0 = bounds[-1]
+        b1 = min(b0 + chunk, len(uniq))
+        cum = np.cumsum(per_src[b0:b1])
+        fit = int(np.searchsorted(cum, max_veh_chunk, "right"))
+        bounds.append(b0 + max(1, min(fit, b1 - b0)))
+    for c0, c1 in zip(bounds[:-1], bounds[1:]):
+        srcs = uniq[c0:c1]
         _, pred = dijkstra(w, directed=True, indices=srcs,
                            return_predecessors=True)
-        row_of = {int(s): k for k, s in enumerate(srcs)}
         lo = np.searchsorted(sorted_orig, srcs[0], "left")
         hi = np.searchsorted(sorted_orig, srcs[-1], "right")
         vids = order[lo:hi]
-        rows = np.array([row_of[int(o)] for o in orig[vids]], np.int64)
-        cur = dest[vids].astype(np.int64)
+        rows = np.searchsorted(srcs, orig[vids])
+        cur = dest[vids].copy()
         steps = []
-        alive = cur != orig[vids]
-        while alive.any():
-            prev = pred[rows[alive], cur[alive]]
+        alive = np.flatnonzero(cur != orig[vids])
+        while len(alive):
+            prev = pred[rows[alive], cur[alive]].astype(np.int64)
             if (prev < 0).any():
                 raise ValueError("destination unreachable")
-            links = np.asarray(
-                lid_dense_rows[prev, cur[alive]]).ravel().astype(np.int64) - 1
+            hit = adj_to[prev] == cur[alive][:, None]
+            links = adj_link[prev, hit.argmax(1)]
             step = np.full(len(vids), -1, np.int64)
             step[alive] = links
             steps.append(step)
             cur[alive] = prev
-            alive = cur != orig[vids]
-        mat = np.array(steps[::-1]) if steps else np.zeros((0, len(vids)))
-        for j, vid in enumerate(vids):
-            col = mat[:, j]
-            paths[vid] = col[col >= 0]
-    lens = np.array([len(p) for p in paths], np.int64)
+            alive = alive[cur[alive] != orig[vids][alive]]
+        if steps:
+            mat = np.array(steps[::-1]).T  # vehicle x position, -1 padded
+            # the path of each vehicle is the tail of its row
+            keep = mat >= 0
+            lens[vids] = keep.sum(1)
+            pieces.append((vids, mat[keep]))
     route_off = np.zeros(n + 1, np.int64)
     np.cumsum(lens, out=route_off[1:])
-    route_links = (np.concatenate(paths).astype(np.int32) if n else
-                   np.zeros(0, np.int32))
+    route_links = np.zeros(int(route_off[-1]), np.int32)
+    for vids, flat in pieces:
+        # flat holds the routes of vids back to back, in vids order
+        starts = route_off[vids]
+        cnt = lens[vids]
+        within = np.arange(len(flat)) - np.repeat(np.cumsum(cnt) - cnt, cnt)
+        route_links[np.repeat(starts, cnt) + within] = flat
     return route_off, route_links
 
 
@@ -324,9 +352,11 @@ def grid_scenario(rows: int, cols: int, n_links: int, n_veh: int, T: int,
                   depart_max: int, seed: int, vmax: int = 5, p="0.2",
                   lanes_range=(1, 3), flags: int = 0, len_sampler=None,
                   depart_sampler=None, sim_seed: Optional[int] = None,
-                  name: str = "grid") -> Scenario:
+                  n_origins: int = 0, name: str = "grid") -> Scenario:
     """Grid network with n_veh vehicles routed by shortest path between
-    distinct uniformly random nodes, departing uniformly in [0, depart_max]."""
+    distinct uniformly random nodes, departing uniformly in [0, depart_max].
+    n_origins > 0 draws the origins from that many random nodes only (trip
+    generation zones), which bounds the routing work of large demands."""
     rng = np.random.Generator(np.random.PCG64(seed))
     frm, to, length, lanes, xy = grid_network(rows, cols, n_links, rng,
                                               lanes_range, len_sampler)
@@ -334,7 +364,11 @@ def grid_scenario(rows: int, cols: int, n_links: int, n_veh: int, T: int,
     n_nodes = rows * cols
     rank, conn_off, conn_out, conn_lo, conn_hi = _ranks_and_conn(
         n_nodes, frm, to, lanes, xy, bool(flags & FLAG_TURN_LANES))
-    orig = rng.integers(0, n_nodes, size=n_veh)
+    if n_origins > 0 and n_origins < n_nodes:
+        zones = rng.choice(n_nodes, size=n_origins, replace=False)
+        orig = zones[rng.integers(0, n_origins, size=n_veh)]
+    else:
+        orig = rng.integers(0, n_nodes, size=n_veh)
     dest = rng.integers(0, n_nodes - 1, size=n_veh)
     dest = dest + (dest >= orig)  # distinct from the origin
     route_off, route_links = shortest_routes(n_nodes, frm, to, length, orig,
@@ -447,3 +481,96 @@ def portland_like(seed: int = 2024, scale: float = 1.0, T: int = 3600,
         nveh = max(1, int(round(200000 * scale)))
     return grid_scenario(rows, cols, links, nveh, T, depart_max, seed,
                          flags=flags, name=f"portland_like(scale={scale})")
+
+
+def _grid_shape(n_links: int):
+    """Near-square grid and an even directed-link count for about n_links
+    links at the Portland-like mean out-degree (20,024 links on 6,006
+    nodes, 3.33)."""
+    nodes = max(4, int(round(n_links / (20024 / 6006))))
+    rows = max(2, int(round(np.sqrt(nodes))))
+    cols = max(2, int(np.ceil(nodes / rows)))
+    nodes = rows * cols
+    und_all = rows * (cols - 1) + cols * (rows - 1)
+    und = min(und_all, max(nodes - 1, n_links // 2))
+    return rows, cols, 2 * und
+
+
+def batched_scenarios(n: int = 64, seed: int = 77, T: int = 3600,
+                      links_lo: int = 1000, links_hi: int = 20000,
+                      veh_per_link=(5, 15), depart_max: int = 1799,
+                      n_origins: int = 256, scale: float = 1.0):
+    """Independent replications of uneven sizes: link counts log-uniform in
+    [links_lo, links_hi], each a Portland-style grid with its own network
+    seed, links x U{5..15} vehicles departing uniformly in [0, depart_max],
+    Philox seed 1000 + k.  `scale` shrinks every size for quick cases."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    for k in range(n):
+        links = int(round(np.exp(rng.uniform(np.log(links_lo),
+                                             np.log(links_hi))) * scale))
+        rows, cols, links = _grid_shape(max(links, 8))
+        per = int(rng.integers(veh_per_link[0], veh_per_link[1] + 1))
+        out.append(grid_scenario(
+            rows, cols, links, max(1, links * per), T, depart_max,
+            seed=int(rng.integers(0, 2**31)), sim_seed=1000 + k,
+            n_origins=n_origins, name=f"batch[{k}]"))
+    return out
+
+
+def serving_pool(n: int = 32, seed: int = 5000, links_lo: int = 1000,
+                 links_hi: int = 50000, veh_per_link: int = 10,
+                 horizon=(600, 3600), n_origins: int = 256,
+                 scale: float = 1.0):
+    """Pre-generated (network, demand) sets for the serving loop: link counts
+    log-uniform in [links_lo, links_hi], 10 vehicles per link, a horizon
+    U{600..3600} steps, departures uniform over its first half, seed
+    5000 + k."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    for k in range(n):
+        links = int(round(np.exp(rng.uniform(np.log(links_lo),
+                                             np.log(links_hi))) * scale))
+        rows, cols, links = _grid_shape(max(links, 8))
+        T = int(rng.integers(horizon[0], horizon[1] + 1))
+        out.append(grid_scenario(
+            rows, cols, links, max(1, links * veh_per_link), T, T // 2,
+            seed=int(rng.integers(0, 2**31)), sim_seed=seed + k,
+            n_origins=n_origins, name=f"pool[{k}]"))
+    return out
+
+
+def large_network(seed: int = 4242, scale: float = 1.0, T: int = 7200,
+                  flags: int = FLAG_LANE_CHANGE | FLAG_TURN_LANES,
+                  n_origins: int = 4096) -> Scenario:
+    """The 200,000-link network: a 245 x 245 grid thinned to 200,000
+    directed links of 1-4 lanes, lengths lognormal with median 60 cells and
+    sigma 0.5 clamped to [6, 1000], 2,000,000 vehicles departing around the
+    morning peak (Gaussian, mean 3,600 s, sigma 1,800 s, redrawn until inside
+    [0, 7199]), lane changing with turn lanes.  `scale` shrinks the grid and
+    the demand."""
+    side = 245
+    links, nveh = 200000, 2000000
+    if scale < 1.0:
+        side = max(3, int(round(245 * np.sqrt(scale))))
+        und_all = 2 * side * (side - 1)
+        links = 2 * max(side * side - 1,
+                        min(und_all, int(round(100000 * scale))))
+        nveh = max(1, int(round(2000000 * scale)))
+
+    def lengths(rng, m):
+        x = np.exp(np.log(60.0) + 0.5 * rng.standard_normal(m))
+        return np.clip(np.rint(x), 6, 1000).astype(np.int64)
+
+    def departs(rng, m):
+        d = rng.normal(3600.0, 1800.0, size=m)
+        bad = (d < 0) | (d > T - 1)
+        while bad.any():
+            d[bad] = rng.normal(3600.0, 1800.0, size=int(bad.sum()))
+            bad = (d < 0) | (d > T - 1)
+        return np.floor(d).astype(np.int32)
+
+    return grid_scenario(side, side, links, nveh, T, T - 1, seed,
+                         lanes_range=(1, 4), flags=flags, len_sampler=lengths,
+                         depart_sampler=departs, n_origins=n_origins,
+                         name=f"large_network(scale={scale})")
