@@ -43,6 +43,12 @@ def make_workload(name: str, steps: int):
                "nodes": scen.n_nodes, "lanes": int(scen.link_lanes.sum()),
                "vehicles": scen.n_veh, "horizon_steps": steps, "vmax": 5,
                "p": 0.2, "lane_change": False}
+    elif name == "large":
+        scen = S.large_network(T=steps)
+        cfg = {"workload": "large_grid_200k_links", "links": scen.n_links,
+               "nodes": scen.n_nodes, "lanes": int(scen.link_lanes.sum()),
+               "vehicles": scen.n_veh, "horizon_steps": steps, "vmax": 5,
+               "p": 0.2, "lane_change": True, "turn_lanes": True}
     elif name == "ring":
         scen = S.ring(T=steps)
         cfg = {"workload": "ring_1000_cells", "vehicles": 150,
@@ -125,6 +131,199 @@ def cpu_baseline(scen, budget_s: float):
                       f"single thread)"}
 
 
+def roofline_from(kt, stats_list, digest=None):
+    """Roofline object of the dominant step kernel from per-kernel times and
+    the summed counters of the scenarios it processed."""
+    kinds = [k for k in ("front", "back", "ring") if kt[k][0] > 0]
+    if not kinds:
+        return None
+    tot = {k: sum(st[k] for st in stats_list)
+           for k in ("c_occ", "veh_updates", "crossings", "exits",
+                     "insertions")}
+    dom = max(kinds, key=lambda k: kt[k][1])
+    launches = kt[dom][0]
+    avg_ms = kt[dom][1] / launches
+    bytes_launch = algorithmic_bytes(dom, tot) / launches
+    achieved = bytes_launch / (avg_ms * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "kernel": f"k_{dom}", "avg_launch_us": avg_ms * 1e3,
+            "algorithmic_bytes_per_launch": bytes_launch,
+            "kernel_sources_digest": digest or kernel_digest(),
+            "kernel_ms": {k: kt[k][1] for k in kinds},
+            "launches": {k: kt[k][0] for k in kinds}}
+
+
+def oracle_sample(scens, budget_s: float):
+    """The oracle over the given scenarios one after another (each from its
+    start) until about budget_s seconds of CPU time are spent."""
+    import oracle
+    t0 = time.perf_counter()
+    upd, steps, used = 0, 0, 0
+    for sc in scens:
+        o = oracle.OracleSim(sc)
+        done = 0
+        while time.perf_counter() - t0 < budget_s and done < sc.T:
+            k = min(25, sc.T - done)
+            o.step(k)
+            done += k
+        upd += o.stats()["veh_updates"]
+        steps += done
+        used += 1
+        if time.perf_counter() - t0 >= budget_s:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": upd / dt, "unit": "vehicle-updates/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"{used} scenario(s) of the same workload from t = 0, "
+                      f"{steps} scenario-steps ({upd} vehicle-updates, "
+                      f"{dt:.1f} s, single thread)"}
+
+
+def bench_batched(args):
+    """64 independent replications of uneven size in one context, stepped
+    together (one launch per sub-step for all of them, 64-step HIP graphs,
+    autotuned tiling), against the plain loop: the same kernels run one
+    scenario at a time, one launch per sub-step, no graph."""
+    import torch
+    from paper_cs_0105004_amd import scenarios as S
+    from paper_cs_0105004_amd.autotune import autotune
+    from paper_cs_0105004_amd.sim import Context
+    log("bench: generating 64 replications")
+    scens = S.batched_scenarios(T=args.steps)
+    n = len(scens)
+    slots = list(range(n))
+    log("bench: autotuning")
+    tune = autotune(scens, warm_steps=min(600, args.steps), trial_steps=128,
+                    reps=2, log=log)
+    ctx = Context(max_slots=n, tile_lanes=tune["tile_lanes"],
+                  back_pieces=tune["back_pieces"],
+                  graph_steps=tune["graph_steps"])
+    for k, sc in enumerate(scens):
+        ctx.load(k, sc)
+    ctx.step(slots, args.warmup)
+    torch.cuda.synchronize()
+    for k, sc in enumerate(scens):
+        ctx.load(k, sc)
+    torch.cuda.synchronize()
+    log(f"bench: timing {args.steps} batched steps")
+    t0 = time.perf_counter()
+    ctx.step(slots, args.steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    stats = [ctx.stats(k) for k in slots]
+    upd = sum(st["veh_updates"] for st in stats)
+    # kernel times of the same run, replayed with events
+    for k, sc in enumerate(scens):
+        ctx.load(k, sc)
+    ctx.profile(True)
+    ctx.step(slots, args.steps)
+    kt = ctx.kernel_times()
+    ctx.profile(False)
+    for k in slots:
+        assert ctx.stats(k)["hash"] == stats[k]["hash"], "replay diverged"
+    roof = roofline_from(kt, stats)
+    ctx.close()
+    log("bench: plain loop")
+    plain = Context(max_slots=1, graph_steps=-1)
+    pwall, pupd = 0.0, 0
+    for k, sc in enumerate(scens):
+        plain.load(0, sc)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        plain.step(0, args.steps)
+        torch.cuda.synchronize()
+        pwall += time.perf_counter() - t1
+        st = plain.stats(0)
+        assert st["hash"] == stats[k]["hash"], "plain loop diverged"
+        pupd += st["veh_updates"]
+    plain.close()
+    cfg = {"workload": "batched_64_replications", "scenarios": n,
+           "links": int(sum(sc.n_links for sc in scens)),
+           "lanes": int(sum(int(sc.link_lanes.sum()) for sc in scens)),
+           "vehicles": int(sum(sc.n_veh for sc in scens)),
+           "horizon_steps": args.steps, "vmax": 5, "p": 0.2,
+           "tile_lanes": tune["tile_lanes"],
+           "graph_steps": tune["graph_steps"]}
+    out = {"metric": METRIC, "value": upd / wall, "unit": "vehicle-updates/s",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": wall * 1e3 / max(args.steps, 1),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "int32", "data": "synthetic", "config": cfg,
+           "sim_real_time_ratio_per_scenario": args.steps / wall,
+           "vehicle_updates": upd, "wall_s": wall,
+           "plain_loop": {"value": pupd / pwall, "wall_s": pwall},
+           "speedup_vs_plain_loop": (upd / wall) / (pupd / pwall),
+           "autotune": tune["trials"], "roofline": roof}
+    if not args.no_cpu_baseline:
+        log(f"bench: oracle sample ({args.cpu_seconds:.0f} s budget)")
+        out["cpu_baseline"] = oracle_sample(scens, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+def bench_serve(args):
+    """Poisson arrivals (4 per second over 60 s) of runs drawn from 32
+    pre-generated (network, demand) sets of 1k-50k links, served by the
+    continuous-batching loop; p50/p99 completion latency and aggregate
+    vehicle-updates/s.  A second, shorter pass with kernel timing gives the
+    roofline position."""
+    import torch
+    from paper_cs_0105004_amd import scenarios as S
+    from paper_cs_0105004_amd.serve import Server, poisson_trace, summarize
+    from paper_cs_0105004_amd.sim import Context
+    log("bench: generating the request pool")
+    pool = S.serving_pool()
+    trace = poisson_trace(pool, rate_per_s=4.0, window_s=args.window)
+    # warm-up: a few requests through a throw-away server
+    srv = Server(max_slots=64, chunk=64)
+    srv.run(trace[:4], realtime=False)
+    torch.cuda.synchronize()
+    log(f"bench: serving {len(trace)} requests")
+    t0 = time.perf_counter()
+    res = srv.run(trace, realtime=True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    srv.close()
+    summ = summarize(res, wall)
+    # a few results checked against the same run alone
+    check = Context(max_slots=1)
+    for r in res[:: max(1, len(res) // 4)]:
+        sc = trace[r.rid].scen
+        check.load(0, sc)
+        check.step(0, sc.T)
+        assert check.stats(0)["hash"] == r.stats["hash"], "mix != alone"
+    check.close()
+    # kernel timing over the first 15 s of the same trace
+    short = [q for q in trace if q.arrival_s <= 15.0]
+    srv = Server(max_slots=64, chunk=64)
+    srv.ctx.profile(True)
+    res2 = srv.run(short, realtime=True)
+    kt = srv.ctx.kernel_times()
+    srv.close()
+    roof = roofline_from(kt, [r.stats for r in res2])
+    cfg = {"workload": "serving_poisson", "rate_per_s": 4.0,
+           "window_s": args.window, "requests": len(trace), "pool_sets": 32,
+           "links_range": [1000, 50000], "vehicles_per_link": 10,
+           "horizon_range": [600, 3600], "max_slots": 64, "chunk_steps": 64}
+    out = {"metric": METRIC, "value": summ["updates_per_s"],
+           "unit": "vehicle-updates/s", "n_gpus": 1, "steps": None,
+           "warmup": 4, "ms_per_step": None, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "int32",
+           "data": "synthetic", "config": cfg,
+           "p50_latency_s": summ["p50_latency_s"],
+           "p99_latency_s": summ["p99_latency_s"],
+           "max_latency_s": summ["max_latency_s"],
+           "vehicle_updates": summ["vehicle_updates"], "wall_s": wall,
+           "roofline": roof}
+    if not args.no_cpu_baseline:
+        log(f"bench: oracle sample ({args.cpu_seconds:.0f} s budget)")
+        out["cpu_baseline"] = oracle_sample([q.scen for q in trace[:3]],
+                                            args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -139,6 +338,8 @@ def main():
                          "percentiles")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     metavar="BYTES", help="only run plain copies of BYTES")
+    ap.add_argument("--window", type=float, default=60.0,
+                    help="serving: seconds of Poisson arrivals")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not "
@@ -152,6 +353,10 @@ def main():
     torch.cuda.set_device(0)
     if args.copy_calibration > 0:
         return copy_calibration(args.copy_calibration)
+    if args.workload == "batched":
+        return bench_batched(args)
+    if args.workload == "serve":
+        return bench_serve(args)
     log(f"bench: generating workload {args.workload}")
     scen, cfg = make_workload(args.workload, args.steps)
     ctx = Context(max_slots=2, tile_lanes=args.tile_lanes)

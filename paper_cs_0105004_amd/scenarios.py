@@ -542,13 +542,13 @@ def serving_pool(n: int = 32, seed: int = 5000, links_lo: int = 1000,
 
 def large_network(seed: int = 4242, scale: float = 1.0, T: int = 7200,
                   flags: int = FLAG_LANE_CHANGE | FLAG_TURN_LANES,
-                  n_origins: int = 4096) -> Scenario:
+                  n_origins: int = 1024) -> Scenario:
     """The 200,000-link network: a 245 x 245 grid thinned to 200,000
     directed links of 1-4 lanes, lengths lognormal with median 60 cells and
     sigma 0.5 clamped to [6, 1000], 2,000,000 vehicles departing around the
     morning peak (Gaussian, mean 3,600 s, sigma 1,800 s, redrawn until inside
-    [0, 7199]), lane changing with turn lanes.  `scale` shrinks the grid and
-    the demand."""
+    [0, 7199]), lane changing with turn lanes.  Origins are drawn from
+    n_origins random zone nodes.  `scale` shrinks the grid and the demand."""
     side = 245
     links, nveh = 200000, 2000000
     if scale < 1.0:

@@ -1,0 +1,164 @@
+"""Batched replications, the autotuner, the serving loop and the load
+feedback, on the GPU through the C ABI, against the CPU oracle and against
+each scenario run alone."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_cs_0105004_amd import scenarios as S
+from parity import assert_same_state, assert_same_stats
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def small_batch():
+    # uneven sizes (about 20-400 links), own seeds and demand per scenario
+    return S.batched_scenarios(n=8, seed=5, T=300, scale=0.02,
+                               n_origins=32)
+
+
+def test_batched_replications_match_oracle(small_batch):
+    from paper_cs_0105004_amd.sim import Context
+    ctx = Context(max_slots=len(small_batch))
+    for k, sc in enumerate(small_batch):
+        ctx.load(k, sc)
+    slots = list(range(len(small_batch)))
+    ctx.step(slots, 100)
+    ctx.step(slots, 200)
+    for k, sc in enumerate(small_batch):
+        o = oracle.OracleSim(sc)
+        o.step(300)
+        assert_same_stats(ctx.stats(k), o.stats(), f"replication {k}")
+        assert_same_state(ctx.state(k), o.state(), f"replication {k}")
+    ctx.close()
+
+
+def test_batched_equals_plain_loop(small_batch):
+    # the plain form: one scenario at a time, kernels launched one by one
+    from paper_cs_0105004_amd.sim import Context
+    batched = Context(max_slots=len(small_batch), tile_lanes=32)
+    for k, sc in enumerate(small_batch):
+        batched.load(k, sc)
+    batched.step(list(range(len(small_batch))), 300)
+    plain = Context(max_slots=1, graph_steps=-1)
+    for k, sc in enumerate(small_batch):
+        plain.load(0, sc)
+        plain.step(0, 300)
+        assert plain.stats(0)["hash"] == batched.stats(k)["hash"], k
+        np.testing.assert_array_equal(plain.state(0)["exit_t"],
+                                      batched.state(k)["exit_t"])
+    batched.close()
+    plain.close()
+
+
+def test_autotune_returns_a_consistent_choice(small_batch):
+    from paper_cs_0105004_amd.autotune import autotune
+    best = autotune(small_batch[:4], warm_steps=50, trial_steps=16, reps=1,
+                    tile_lanes=(8, 32), graph_steps=(16, 64))
+    assert best["tile_lanes"] in (8, 32) and best["graph_steps"] in (16, 64)
+    assert len(best["trials"]) == 3  # 2 tile sizes, then 1 new graph size
+    assert best["us_per_step"] == min(t["us_per_step"] for t in best["trials"]
+                                      if t["tile_lanes"] == best["tile_lanes"]
+                                      and t["graph_steps"] == best["graph_steps"])
+    single = autotune(small_batch[:1], warm_steps=20, trial_steps=8, reps=1,
+                      tile_lanes=(16,), back_pieces=(1, 4), graph_steps=(8,))
+    assert single["back_pieces"] in (1, 4)
+
+
+@pytest.fixture(scope="module")
+def pool():
+    return S.serving_pool(n=5, seed=11, scale=0.01, horizon=(60, 240),
+                          n_origins=16)
+
+
+def _alone(scen):
+    from paper_cs_0105004_amd.sim import Context
+    ctx = Context(max_slots=1)
+    ctx.load(0, scen)
+    ctx.step(0, scen.T)
+    out = ctx.stats(0), ctx.state(0)["exit_t"]
+    ctx.close()
+    return out
+
+
+def test_serving_results_equal_alone_and_oracle(pool):
+    from paper_cs_0105004_amd.serve import Server, poisson_trace
+    trace = poisson_trace(pool, rate_per_s=60.0, window_s=0.3, seed=2)
+    assert len(trace) >= 8
+    srv = Server(max_slots=6, chunk=32)
+    res = srv.run(trace)
+    srv.close()
+    assert sorted(r.rid for r in res) == list(range(len(trace)))
+    alone = {}
+    for r in res:
+        sc = trace[r.rid].scen
+        if id(sc) not in alone:
+            alone[id(sc)] = _alone(sc)
+            o = oracle.OracleSim(sc)
+            o.step(sc.T)
+            assert_same_stats(alone[id(sc)][0], o.stats(), sc.name)
+            np.testing.assert_array_equal(alone[id(sc)][1], o.state()["exit_t"])
+        st, ex = alone[id(sc)]
+        assert r.stats["hash"] == st["hash"], r.rid
+        assert r.stats["veh_updates"] == st["veh_updates"], r.rid
+        np.testing.assert_array_equal(r.exit_t, ex)
+        assert r.latency_s >= 0 and r.done_s >= r.admitted_s
+
+
+def test_serving_admission_respects_the_budget(pool):
+    from paper_cs_0105004_amd.serve import Request, Server
+    from paper_cs_0105004_amd.sim import Context
+    probe = Context(max_slots=1)
+    fps = [probe.footprint(sc) for sc in pool]
+    probe.close()
+    budget = max(fps) + min(fps)  # the largest fits, never all at once
+    reqs = [Request(k, 0.0, pool[k % len(pool)]) for k in range(8)]
+    srv = Server(max_slots=8, budget_bytes=budget, chunk=16)
+    res = srv.run(reqs, realtime=False)
+    srv.close()
+    assert len(res) == 8
+    # replay the admissions: at every admission the admitted runs still
+    # active must fit the budget together
+    events = sorted([(r.admitted_s, 1, r.footprint) for r in res] +
+                    [(r.done_s, 0, -r.footprint) for r in res])
+    used = 0
+    for _, _, d in events:
+        used += d
+        assert used <= budget
+    for r in res:
+        st, ex = _alone(reqs[r.rid].scen)
+        assert r.stats["hash"] == st["hash"]
+
+
+def test_serving_rejects_a_request_larger_than_the_budget(pool):
+    from paper_cs_0105004_amd.serve import Request, Server
+    srv = Server(max_slots=2, budget_bytes=1024)
+    with pytest.raises(RuntimeError, match="budget"):
+        srv.run([Request(0, 0.0, pool[0])], realtime=False)
+    srv.close()
+
+
+def test_link_cost_feedback_retiles_without_changing_results():
+    # the paper's adaptive load balancing: costs measured in one run weight
+    # the tiling of the next; the trajectory must not change
+    from paper_cs_0105004_amd.sim import Context
+    scen = S.portland_like(scale=0.05, T=400)
+    ctx = Context(max_slots=2, tile_lanes=8)
+    ctx.load(0, scen)
+    ctx.step(0, 400)
+    cost = ctx.link_costs(0)
+    assert cost.shape == (scen.n_links,) and (cost >= 0).all()
+    assert cost.sum() > 0
+    st0 = ctx.state(0)
+    base_tiles = ctx.tiling(0)
+    ctx.load(1, scen, link_cost=cost)
+    fed_tiles = ctx.tiling(1)
+    assert fed_tiles["n_lanes"] == base_tiles["n_lanes"]
+    # the measured weights move the tile boundaries
+    assert (fed_tiles["n_tiles"], fed_tiles["e_dmn"], fed_tiles["e_tile"]) != \
+        (base_tiles["n_tiles"], base_tiles["e_dmn"], base_tiles["e_tile"])
+    ctx.step(1, 400)
+    assert ctx.stats(1)["hash"] == ctx.stats(0)["hash"]
+    assert_same_state(ctx.state(1), st0, "re-tiled run")
+    ctx.close()
