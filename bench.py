@@ -63,13 +63,18 @@ def make_workload(name: str, steps: int):
 # vehicle's int32 id read and written, 16 B per crossing or trip end for its
 # route entry, exit time and handoff record, 8 B per vehicle leaving parking):
 #   B(t) = 2*C_occ(t) + 8*N(t) + 16*X(t) + 8*I(t)
-# The move kernel does the first three terms, the front kernel the last.
+# The move kernel does the first three terms, the front kernel the last;
+# the one-kernel step does all four.
 def algorithmic_bytes(kind, st):
     if kind == "back":
         return (2.0 * st["c_occ"] + 8.0 * st["veh_updates"]
                 + 16.0 * (st["crossings"] + st["exits"]))
     if kind == "front":
         return 8.0 * st["insertions"]
+    if kind == "step":  # one kernel does the whole step
+        return (2.0 * st["c_occ"] + 8.0 * st["veh_updates"]
+                + 16.0 * (st["crossings"] + st["exits"])
+                + 8.0 * st["insertions"])
     return 2.0 * st["c_occ"] + 8.0 * st["veh_updates"]  # ring: one launch
 
 
@@ -134,7 +139,7 @@ def cpu_baseline(scen, budget_s: float):
 def roofline_from(kt, stats_list, digest=None):
     """Roofline object of the dominant step kernel from per-kernel times and
     the summed counters of the scenarios it processed."""
-    kinds = [k for k in ("front", "back", "ring") if kt[k][0] > 0]
+    kinds = [k for k in ("front", "back", "ring", "step") if kt[k][0] > 0]
     if not kinds:
         return None
     tot = {k: sum(st[k] for st in stats_list)
@@ -400,7 +405,7 @@ def main():
     tiling = ctx.tiling(0)
     K = max(args.steps, 1)
     roof = None
-    kinds = [k for k in ("front", "back", "ring") if kt[k][0] > 0]
+    kinds = [k for k in ("front", "back", "ring", "step") if kt[k][0] > 0]
     if kinds:
         dom = max(kinds, key=lambda k: kt[k][1])
         launches = kt[dom][0]

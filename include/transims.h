@@ -79,7 +79,11 @@ typedef struct {
                            0 = default (4)                                  */
   int32_t graph_steps;  /* steps per HIP graph replay in sim_step; 0 =
                            default (64); < 0 = launch kernels one by one    */
-  int32_t reserved;
+  int32_t step_mode;    /* 0 = one kernel per step for scenarios without
+                           lane changes whose links all have >= 2*vmax
+                           cells, two kernels (lane-change / move sub-step)
+                           otherwise; 1 = always two kernels.  Results are
+                           the same either way.                             */
 } sim_config;
 
 /* Per-scenario parameters. */
@@ -212,15 +216,16 @@ sim_status sim_tiling_info(const sim_ctx* ctx, int32_t slot, sim_tiling* out);
    itself).  With graph_steps < 0, and for the ring kernel, each launch is
    bracketed by two events on the context stream instead (no correction).
    sim_kernel_times waits for the stream, reports per kernel kind (0 = front
-   / lane-change sub-step, 1 = back / move sub-step, 2 = ring) the number of
-   launches and their summed duration, and resets the sums. */
+   / lane-change sub-step, 1 = back / move sub-step, 2 = ring, 3 = one-kernel
+   step) the number of launches and their summed duration, and resets the
+   sums. */
 typedef struct {
   int64_t launches;
   double total_ms;
 } sim_kernel_time;
 
 sim_status sim_profile(sim_ctx* ctx, int32_t enable);
-sim_status sim_kernel_times(sim_ctx* ctx, sim_kernel_time out[3]);
+sim_status sim_kernel_times(sim_ctx* ctx, sim_kernel_time out[4]);
 
 /* Forgets the slot (its workspace may then be released by the caller). */
 sim_status sim_unload(sim_ctx* ctx, int32_t slot);

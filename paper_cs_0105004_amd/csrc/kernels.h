@@ -21,9 +21,15 @@ hipError_t launch_front(const DevScen* d_descs, int slot, const int4* d_work,
 // n_extra wavefronts for the runs of heavy tiles the front kernel listed.
 hipError_t launch_back(const DevScen* d_descs, int slot, const int4* d_work,
                        int n_work, int n_extra, int step, hipStream_t s);
+// One kernel for the whole step, for slots whose state is kept by step
+// parity (DevScen::fused); work items as above, one wavefront each.
+hipError_t launch_step(const DevScen* d_descs, int slot, const int4* d_work,
+                       int n_work, int step, hipStream_t s);
 // Host stubs of the step kernels, for building HIP graphs:
+//   step(descs, slot, work, step),
 //   front(descs, slot, work, pieces, step), back(descs, slot, work, n_work,
 //   step), advance(descs, slots, n, k)
+void* step_kernel(bool batched);
 void* front_kernel(bool batched);
 void* back_kernel(bool batched);
 void* advance_kernel();

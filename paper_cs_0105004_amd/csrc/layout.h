@@ -109,8 +109,20 @@ enum : int {
 //       ends at the node), y = x of the rearmost vehicle (len if empty),
 //   z = the lane's queue (hc) as the move finds it
 
+// One kernel per step.  Without lane changes, and with every link at least
+// 2*vmax cells long, each input of a step that another tile produces is
+// final when the previous step ends: the lead vehicles that compete at a
+// node (a vehicle that arrives in a step lands within vmax-1 cells of the
+// link start, so it cannot reach the node region in that step), their
+// claims (made by the previous step's move), and the state of a target
+// link's lanes and parking queue.  Those arrays are then kept twice and
+// indexed by step parity: in step t a kernel reads buffer t&1 of lane_state,
+// claim and qnext and buffer (t-1)&1 of the handoff slots, and writes the
+// other one.  With `fused` == 0 only buffer 0 is used.
+
 struct DevScen {
   uint32_t flags;
+  int32_t fused;  // 1: one kernel per step, parity-buffered state
   int32_t vmax;
   uint32_t key0, key1;  // Philox key = seed
   uint64_t slow_thr;
@@ -135,6 +147,8 @@ struct DevScen {
   // wait_rec and a copy of that record (id -1: to be fetched again)
   int32_t* lane_qhead;
   int4* lane_qrec;
+  // fused: depart of the link's queue head (INT32_MAX: empty), at lane 0
+  int32_t* qnext;
   // vehicle records
   uint2* hot;
   int2* cold;

@@ -63,6 +63,27 @@ std::vector<int2> pack_tiles(const std::vector<int32_t>& lanes, int tile_lanes) 
   return tiles;
 }
 
+std::vector<int2> pack_tiles(const std::vector<int32_t>& lanes,
+                             const std::vector<int32_t>& len, int tile_lanes,
+                             int64_t max_cells) {
+  std::vector<int2> tiles;
+  int32_t first = 0, cur = 0;
+  int64_t cells = 0;
+  for (size_t l = 0; l < lanes.size(); ++l) {
+    const int64_t c = (int64_t)lanes[l] * len[l];
+    if (cur > 0 && (cur + lanes[l] > tile_lanes || cells + c > max_cells)) {
+      tiles.push_back(make_int2(first, cur));
+      first += cur;
+      cur = 0;
+      cells = 0;
+    }
+    cur += lanes[l];
+    cells += c;
+  }
+  if (cur > 0) tiles.push_back(make_int2(first, cur));
+  return tiles;
+}
+
 std::vector<int2> xcd_interleave(const std::vector<int2>& tiles, int domains) {
   const int64_t n = (int64_t)tiles.size();
   std::vector<int64_t> start(domains + 1);

@@ -28,6 +28,11 @@ void orb_order(std::vector<int32_t>& order, const std::vector<double>& mx,
 // Packs consecutive links (lanes[l] lanes each) into tiles of at most
 // tile_lanes lanes; a tile never splits a link.  Returns {first lane, lanes}.
 std::vector<int2> pack_tiles(const std::vector<int32_t>& lanes, int tile_lanes);
+// The same, and a tile also takes no link that would bring it past max_cells
+// cells (len x lanes), unless the tile is still empty.
+std::vector<int2> pack_tiles(const std::vector<int32_t>& lanes,
+                             const std::vector<int32_t>& len, int tile_lanes,
+                             int64_t max_cells);
 
 // Deals a list of tiles to `domains` XCDs: XCD x gets the x-th contiguous
 // chunk, and position p of the result runs on XCD p mod domains.

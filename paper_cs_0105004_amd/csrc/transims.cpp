@@ -25,6 +25,9 @@ constexpr int kLcMaxLen = 2048;  // longest multi-lane link that changes lanes
 constexpr int kDefaultTileLanes = 16;
 constexpr int kDefaultBackPieces = 4;
 constexpr int kDefaultGraphSteps = 64;
+// one-kernel steps: a tile also stops at this many cells, so that no
+// wavefront is left with a much longer queue of vehicles than the rest
+constexpr int kFusedTileCells = 1024;
 
 struct Slot {
   bool net = false, veh = false, ring = false;
@@ -43,6 +46,7 @@ struct Slot {
   DevScen d{};
   int32_t t = 0;
   int32_t lc_cells = 0;
+  bool fused = false;  // one kernel per step (state kept by step parity)
   sim_tiling tiling{};
 };
 
@@ -61,7 +65,11 @@ struct sim_ctx {
   unsigned long long* d_stats = nullptr;
   std::vector<int32_t> work_key;
   int n_work = 0, n_net = 0, n_ring = 0, lc_cells = 0;
-  int single_slot = -1;  // the only network slot of the work list, or -1
+  // the work list holds the tiles of fused slots first (n_fwork items, one
+  // kernel per step), then those of two-kernel slots
+  int n_fwork = 0;
+  int fused_slot = -1;   // the only fused slot of the work list, or -1
+  int single_slot = -1;  // the only two-kernel slot of the work list, or -1
   int n_extra = 0;       // extra move wavefronts of the single slot
   // a HIP graph of graph_steps steps of the current work list
   hipGraphExec_t graph = nullptr;
@@ -75,8 +83,9 @@ struct sim_ctx {
   hipGraphExec_t pgraph = nullptr;
   int pgraph_k = 0;
   std::vector<hipEvent_t> gev;
-  int64_t acc_launches[3] = {0, 0, 0};
-  double acc_ms[3] = {0, 0, 0};
+  std::vector<int> gkind;  // kernel kind of each interval of a profiled graph
+  int64_t acc_launches[4] = {0, 0, 0, 0};
+  double acc_ms[4] = {0, 0, 0, 0};
   std::string err;
 };
 
@@ -133,11 +142,12 @@ void carve_network(Carve& cv, const NetDims& nd, DevScen& d, bool ring) {
   const int64_t L = nd.L, Q = nd.Q;
   d.link_ext = cv.take<int32_t>(L);
   d.lane_info = cv.take<int4>(Q);
-  d.lane_state = cv.take<int4>(Q);
+  d.lane_state = cv.take<int4>(2 * Q);  // two step-parity buffers
   d.lane_sum = cv.take<int4>(Q);
-  d.claim = cv.take<int32_t>(Q);
-  d.hand_a = cv.take<int4>(Q);
-  d.hand_b = cv.take<int32_t>(Q);
+  d.claim = cv.take<int32_t>(2 * Q);
+  d.hand_a = cv.take<int4>(2 * Q);
+  d.hand_b = cv.take<int32_t>(2 * Q);
+  d.qnext = cv.take<int32_t>(2 * Q);
   d.lane_qhead = cv.take<int32_t>(Q);
   d.lane_qrec = cv.take<int4>(Q);
   d.hot = cv.take<uint2>(ring ? 0 : nd.rec);
@@ -266,6 +276,7 @@ extern "C" sim_status sim_create(const sim_config* cfg, sim_ctx** out) {
   if (cfg->max_slots < 1 || cfg->max_slots > 65536) return SIM_E_INVAL;
   if (cfg->tile_lanes < 0 || cfg->tile_lanes > kMaxTileLanes) return SIM_E_INVAL;
   if (cfg->back_pieces < 0 || cfg->back_pieces > 8) return SIM_E_INVAL;
+  if (cfg->step_mode < 0 || cfg->step_mode > 1) return SIM_E_INVAL;
   sim_ctx* c = new (std::nothrow) sim_ctx();
   if (!c) return SIM_E_CAPACITY;
   c->cfg = *cfg;
@@ -380,7 +391,14 @@ extern "C" sim_status sim_load_network(sim_ctx* c, int32_t slot,
     S.n_cells += (int64_t)S.len[i] * S.lanes[i];
   }
   S.n_lanes = q;
-  S.ftiles = pack_tiles(S.lanes, c->cfg.tile_lanes);
+  {
+    int32_t min_len = INT32_MAX;
+    for (int32_t i = 0; i < L; ++i) min_len = std::min(min_len, S.len[i]);
+    S.fused = !S.ring && c->cfg.step_mode == 0 &&
+              !(p->flags & SIM_FLAG_LANE_CHANGE) && min_len >= 2 * p->vmax;
+  }
+  S.ftiles = S.fused ? pack_tiles(S.lanes, S.len, c->cfg.tile_lanes, kFusedTileCells)
+                     : pack_tiles(S.lanes, c->cfg.tile_lanes);
   S.n_ftiles = (int32_t)S.ftiles.size();
   S.tiles = S.ftiles;  // the move sub-step splits these tiles further
   S.n_tiles = S.n_ftiles;
@@ -444,7 +462,8 @@ extern "C" sim_status sim_load_network(sim_ctx* c, int32_t slot,
   d.n_lanes = S.n_lanes;
   d.n_tiles = S.n_tiles;
   d.n_ftiles = S.n_ftiles;
-  d.xcap = S.ring ? 0 : (int32_t)extra_cap(S.n_ftiles, c->cfg.back_pieces);
+  d.xcap = (S.ring || S.fused) ? 0 : (int32_t)extra_cap(S.n_ftiles, c->cfg.back_pieces);
+  d.fused = S.fused ? 1 : 0;
   d.lc_cells = S.lc_cells;
   d.ring_L = S.ring ? net->len[0] : 0;
   hipStream_t s = c->stream;
@@ -475,17 +494,18 @@ extern "C" sim_status sim_load_vehicles(sim_ctx* c, int32_t slot,
   hipStream_t s = c->stream;
   // per-run device state starts empty
   {
-    std::vector<int4> hand_a(S.n_lanes, make_int4(kTagNone, 0, 0, 0));
-    HIPCHK(c, up(d.hand_a, hand_a.data(), S.n_lanes, s));
-    HIPCHK(c, hipMemsetAsync(d.lane_state, 0, sizeof(int4) * S.n_lanes, s));
+    std::vector<int4> hand_a(2 * S.n_lanes, make_int4(kTagNone, 0, 0, 0));
+    HIPCHK(c, up(d.hand_a, hand_a.data(), 2 * S.n_lanes, s));
+    HIPCHK(c, hipMemsetAsync(d.lane_state, 0, sizeof(int4) * 2 * S.n_lanes, s));
     HIPCHK(c, hipMemsetAsync(d.tile_ctr, 0, sizeof(long long) * C_N * S.n_lanes, s));
     HIPCHK(c, hipMemsetAsync(d.ftile_ctr, 0, sizeof(long long) * C_N * S.n_ftiles, s));
     HIPCHK(c, hipMemsetAsync(d.xcount, 0, sizeof(int32_t) * 2, s));
     HIPCHK(c, hipMemsetAsync(d.tile_np, 0, sizeof(int32_t) * S.n_lanes, s));
     HIPCHK(c, hipMemsetAsync(d.ring_ctr, 0, sizeof(long long) * C_N, s));
     HIPCHK(c, hipMemsetAsync(d.err, 0, sizeof(uint32_t), s));
-    std::vector<int32_t> claim(S.n_lanes, INT32_MAX);
-    HIPCHK(c, up(d.claim, claim.data(), S.n_lanes, s));
+    std::vector<int32_t> none(2 * S.n_lanes, INT32_MAX);
+    HIPCHK(c, up(d.claim, none.data(), 2 * S.n_lanes, s));
+    HIPCHK(c, up(d.qnext, none.data(), 2 * S.n_lanes, s));
     HIPCHK(c, hipStreamSynchronize(s));
   }
 
@@ -679,7 +699,28 @@ extern "C" sim_status sim_load_vehicles(sim_ctx* c, int32_t slot,
       HIPCHK(c, up(d.hot + run_slot[r], hot.data() + run_first[r], run_len[r], s));
       HIPCHK(c, up(d.cold + run_slot[r], cold.data() + run_first[r], run_len[r], s));
     }
-    HIPCHK(c, up(d.lane_state, state.data(), S.n_lanes, s));
+    // a fused slot keeps the state of step t in buffer t & 1, with the
+    // claims of the lead vehicles near a node registered for that step
+    const int64_t cur = S.fused ? (int64_t)(v->t0 & 1) * S.n_lanes : 0;
+    HIPCHK(c, up(d.lane_state + cur, state.data(), S.n_lanes, s));
+    std::vector<int32_t> qn, cl;
+    if (S.fused) {
+      qn.assign(S.n_lanes, INT32_MAX);
+      for (int32_t l = 0; l < L; ++l)
+        if (wait_cnt[l] < wait_cnt[l + 1]) qn[S.lane0[l]] = v->depart[wid[wait_cnt[l]]];
+      cl.assign(S.n_lanes, INT32_MAX);
+      for (int32_t qq = 0; qq < S.n_lanes; ++qq) {
+        if (hc_cnt(state[qq].w) == 0) continue;
+        const uint32_t meta = (uint32_t)S.lane_info[qq].y;
+        const uint32_t xvf = (uint32_t)state[qq].x, ni = (uint32_t)state[qq].y;
+        if (lmeta_len(meta) - 1 - xvf_x(xvf) >= vmax || (xvf_fl(xvf) & kFlLast)) continue;
+        const int k = lmeta_k(meta);
+        const int32_t tgt = rinfo_lane0(ni) + std::min(k, rinfo_lanes(ni) - 1);
+        cl[tgt] = std::min(cl[tgt], lmeta_rank(meta) * 8 + k);
+      }
+      HIPCHK(c, up(d.qnext + cur, qn.data(), S.n_lanes, s));
+      HIPCHK(c, up(d.claim + cur, cl.data(), S.n_lanes, s));
+    }
     HIPCHK(c, hipStreamSynchronize(s));
     S.n_route = R;
   }
@@ -703,20 +744,28 @@ sim_status build_work(sim_ctx* c, const std::vector<int32_t>& net,
   if (key == c->work_key) return SIM_OK;
   // all tiles of all network slots, dealt to the 8 XCDs in contiguous chunks
   // (workgroup w runs on XCD w mod 8); front tiles first, then back tiles
+  // (fused slots' tiles first: they run in their own kernel)
   int lc = 0;
-  std::vector<int2> all;
-  for (int32_t sl : net) {
-    const Slot& S = c->slots[sl];
-    for (int32_t t = 0; t < S.n_ftiles; ++t) all.push_back(make_int2(sl, t));
-    lc = std::max(lc, S.lc_cells);
+  std::vector<int4> work;
+  std::vector<int32_t> fused_slots, two_slots;
+  for (int pass = 0; pass < 2; ++pass) {
+    std::vector<int2> all;
+    for (int32_t sl : net) {
+      const Slot& S = c->slots[sl];
+      if (S.fused != (pass == 0)) continue;
+      (pass == 0 ? fused_slots : two_slots).push_back(sl);
+      for (int32_t t = 0; t < S.n_ftiles; ++t) all.push_back(make_int2(sl, t));
+      if (pass == 1) lc = std::max(lc, S.lc_cells);
+    }
+    const std::vector<int2> dealt = xcd_interleave(all, 8);
+    for (size_t k = 0; k < dealt.size(); ++k) {
+      const int2 tl = c->slots[dealt[k].x].ftiles[dealt[k].y];
+      work.push_back(make_int4(dealt[k].x, tl.x, tl.y, dealt[k].y));
+    }
+    if (pass == 0) c->n_fwork = (int)work.size();
   }
-  const std::vector<int2> dealt = xcd_interleave(all, 8);
-  std::vector<int4> work(dealt.size());
-  for (size_t k = 0; k < dealt.size(); ++k) {
-    const int2 tl = c->slots[dealt[k].x].ftiles[dealt[k].y];
-    work[k] = make_int4(dealt[k].x, tl.x, tl.y, dealt[k].y);
-  }
-  c->single_slot = net.size() == 1 ? net[0] : -1;
+  c->fused_slot = fused_slots.size() == 1 ? fused_slots[0] : -1;
+  c->single_slot = two_slots.size() == 1 ? two_slots[0] : -1;
   c->n_extra = c->single_slot >= 0 ? c->slots[c->single_slot].d.xcap : 0;
   if (c->graph) {
     (void)hipGraphExecDestroy(c->graph);
@@ -762,30 +811,39 @@ sim_status build_work(sim_ctx* c, const std::vector<int32_t>& net,
 constexpr int kLeadEvents = 8;  // back-to-back events that time an event
 
 sim_status build_graph(sim_ctx* c, int K, bool profiled, hipGraphExec_t* out) {
+  const int n_fw = c->n_fwork, n_tw = c->n_work - c->n_fwork;
+  const int per_step = (n_fw > 0 ? 1 : 0) + (n_tw > 0 ? 2 : 0);
   if (profiled) {
-    while (c->gev.size() < (size_t)(2 * K + kLeadEvents)) {
+    while (c->gev.size() < (size_t)(per_step * K + kLeadEvents)) {
       hipEvent_t ev;
       HIPCHK(c, hipEventCreate(&ev));
       c->gev.push_back(ev);
     }
+    c->gkind.clear();
   }
   hipGraph_t g = nullptr;
   HIPCHK(c, hipGraphCreate(&g, 0));
+  // one-kernel slots
+  const bool fbatched = c->fused_slot < 0;
+  int fslot = fbatched ? 0 : c->fused_slot;
+  const int4* fwork = c->d_work;
+  // two-kernel slots
   const bool batched = c->single_slot < 0;
   int slot = batched ? 0 : c->single_slot;
   int pieces = batched ? 1 : c->cfg.back_pieces;
-  int n_work = c->n_work;
   const DevScen* descs = c->d_descs;
-  const int4* work = c->d_work;
+  const int4* work = c->d_work + n_fw;
+  int n_work = n_tw;
   hipGraphNode_t prev = nullptr;
   hipError_t e = hipSuccess;
   int n_ev = 0;
-  auto mark = [&]() {
+  auto mark = [&](int kind) {
     if (e != hipSuccess || !profiled) return;
     hipGraphNode_t node;
     e = hipGraphAddEventRecordNode(&node, g, prev ? &prev : nullptr, prev ? 1 : 0,
                                    c->gev[n_ev++]);
     prev = node;
+    if (kind >= 0) c->gkind.push_back(kind);
   };
   auto add = [&](void* fn, int grid, int block, size_t shmem, void** args) {
     if (e != hipSuccess) return;
@@ -800,16 +858,23 @@ sim_status build_graph(sim_ctx* c, int K, bool profiled, hipGraphExec_t* out) {
     e = hipGraphAddKernelNode(&node, g, prev ? &prev : nullptr, prev ? 1 : 0, &kp);
     prev = node;
   };
-  for (int j = 0; j < kLeadEvents; ++j) mark();
+  for (int j = 0; j < kLeadEvents; ++j) mark(-1);
   for (int s = 0; s < K; ++s) {
     int step = s;
-    void* fa[] = {&descs, &slot, &work, &pieces, &step};
-    add(front_kernel(batched), c->n_work, kFrontThreads, (size_t)3 * c->lc_cells, fa);
-    mark();
-    void* ba[] = {&descs, &slot, &work, &n_work, &step};
-    add(back_kernel(batched), c->n_work + (batched ? 0 : c->n_extra),
-        kBackThreadsPerPiece, 0, ba);
-    mark();
+    if (n_fw > 0) {
+      void* sa[] = {&descs, &fslot, &fwork, &step};
+      add(step_kernel(fbatched), n_fw, kWave, 0, sa);
+      mark(3);
+    }
+    if (n_tw > 0) {
+      void* fa[] = {&descs, &slot, &work, &pieces, &step};
+      add(front_kernel(batched), n_tw, kFrontThreads, (size_t)3 * c->lc_cells, fa);
+      mark(0);
+      void* ba[] = {&descs, &slot, &work, &n_work, &step};
+      add(back_kernel(batched), n_tw + (batched ? 0 : c->n_extra),
+          kBackThreadsPerPiece, 0, ba);
+      mark(1);
+    }
   }
   DevScen* mdescs = c->d_descs;
   const int* list = c->d_list;
@@ -824,8 +889,9 @@ sim_status build_graph(sim_ctx* c, int K, bool profiled, hipGraphExec_t* out) {
   return SIM_OK;
 }
 
-// Replays a profiled graph of K steps once and adds its per-kernel times.
-sim_status run_profiled(sim_ctx* c, hipGraphExec_t ex, int K) {
+// Replays a profiled graph once and adds its per-kernel times (the graph
+// last built with profiled = true).
+sim_status run_profiled(sim_ctx* c, hipGraphExec_t ex) {
   HIPCHK(c, hipGraphLaunch(ex, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   double ev = 0;  // mean cost of one event node
@@ -836,11 +902,11 @@ sim_status run_profiled(sim_ctx* c, hipGraphExec_t ex, int K) {
   }
   ev /= (kLeadEvents - 1);
   const int e0 = kLeadEvents - 1;  // the event before the first kernel
-  for (int j = 0; j < 2 * K; ++j) {
+  for (size_t j = 0; j < c->gkind.size(); ++j) {
     float ms = 0;
     HIPCHK(c, hipEventElapsedTime(&ms, c->gev[e0 + j], c->gev[e0 + j + 1]));
-    c->acc_launches[j & 1]++;
-    c->acc_ms[j & 1] += std::max(0.0, (double)ms - ev);
+    c->acc_launches[c->gkind[j]]++;
+    c->acc_ms[c->gkind[j]] += std::max(0.0, (double)ms - ev);
   }
   return SIM_OK;
 }
@@ -876,7 +942,7 @@ extern "C" sim_status sim_profile(sim_ctx* c, int32_t enable) {
   return SIM_OK;
 }
 
-extern "C" sim_status sim_kernel_times(sim_ctx* c, sim_kernel_time out[3]) {
+extern "C" sim_status sim_kernel_times(sim_ctx* c, sim_kernel_time out[4]) {
   if (!c) return SIM_E_INVAL;
   if (!out) return fail(c, SIM_E_INVAL, "out is NULL");
   HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -887,7 +953,7 @@ extern "C" sim_status sim_kernel_times(sim_ctx* c, sim_kernel_time out[3]) {
     c->acc_ms[c->event_kind[p]] += ms;
   }
   c->n_pairs = 0;
-  for (int k = 0; k < 3; ++k) {
+  for (int k = 0; k < 4; ++k) {
     out[k] = sim_kernel_time{c->acc_launches[k], c->acc_ms[k]};
     c->acc_launches[k] = 0;
     c->acc_ms[k] = 0;
@@ -924,22 +990,28 @@ extern "C" sim_status sim_step(sim_ctx* c, const int32_t* slots, int32_t n_slots
       if (n_steps >= K && (!c->pgraph || c->pgraph_k != K)) {
         if (c->pgraph) (void)hipGraphExecDestroy(c->pgraph);
         c->pgraph = nullptr;
+        c->pgraph_k = 0;
         st = build_graph(c, K, true, &c->pgraph);
         if (st != SIM_OK) return st;
         c->pgraph_k = K;
       }
       for (; done + K <= n_steps; done += K) {
-        st = run_profiled(c, c->pgraph, K);
+        st = run_profiled(c, c->pgraph);
         if (st != SIM_OK) return st;
       }
       if (done < n_steps) {
+        // the event kinds belong to the graph built last: rebuild the
+        // cached one afterwards
         hipGraphExec_t rg = nullptr;
         st = build_graph(c, n_steps - done, true, &rg);
         if (st != SIM_OK) return st;
-        st = run_profiled(c, rg, n_steps - done);
+        st = run_profiled(c, rg);
         (void)hipGraphExecDestroy(rg);
         if (st != SIM_OK) return st;
         done = n_steps;
+        if (c->pgraph) (void)hipGraphExecDestroy(c->pgraph);
+        c->pgraph = nullptr;
+        c->pgraph_k = 0;
       }
     } else if (K > 0 && n_steps >= K) {
       if (!c->graph || c->graph_k != K) {
@@ -952,17 +1024,26 @@ extern "C" sim_status sim_step(sim_ctx* c, const int32_t* slots, int32_t n_slots
       for (; done + K <= n_steps; done += K) HIPCHK(c, hipGraphLaunch(c->graph, c->stream));
     }
     const int32_t rest = n_steps - done;
+    const int n_fw = c->n_fwork, n_tw = c->n_work - c->n_fwork;
     for (int32_t s = 0; s < rest; ++s) {
-      st = timed(c, 0, [&] {
-        return launch_front(c->d_descs, c->single_slot, c->d_work, c->n_work,
-                            c->cfg.back_pieces, s, c->lc_cells, c->stream);
-      });
-      if (st != SIM_OK) return st;
-      st = timed(c, 1, [&] {
-        return launch_back(c->d_descs, c->single_slot, c->d_work, c->n_work,
-                           c->n_extra, s, c->stream);
-      });
-      if (st != SIM_OK) return st;
+      if (n_fw > 0) {
+        st = timed(c, 3, [&] {
+          return launch_step(c->d_descs, c->fused_slot, c->d_work, n_fw, s, c->stream);
+        });
+        if (st != SIM_OK) return st;
+      }
+      if (n_tw > 0) {
+        st = timed(c, 0, [&] {
+          return launch_front(c->d_descs, c->single_slot, c->d_work + n_fw, n_tw,
+                              c->cfg.back_pieces, s, c->lc_cells, c->stream);
+        });
+        if (st != SIM_OK) return st;
+        st = timed(c, 1, [&] {
+          return launch_back(c->d_descs, c->single_slot, c->d_work + n_fw, n_tw,
+                             c->n_extra, s, c->stream);
+        });
+        if (st != SIM_OK) return st;
+      }
     }
     if (rest > 0)
       HIPCHK(c, launch_advance(c->d_descs, c->d_list, c->n_net, rest, c->stream));

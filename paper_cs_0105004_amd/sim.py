@@ -34,7 +34,7 @@ class sim_config(C.Structure):
     _fields_ = [("abi_version", C.c_int32), ("max_slots", C.c_int32),
                 ("stream", C.c_void_p), ("tile_lanes", C.c_int32),
                 ("back_pieces", C.c_int32), ("graph_steps", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("step_mode", C.c_int32)]
 
 
 class sim_params(C.Structure):
@@ -175,7 +175,8 @@ class Context:
     """A libtransims context on the current GPU with `max_slots` slots."""
 
     def __init__(self, max_slots: int = 1, tile_lanes: int = 0,
-                 back_pieces: int = 0, graph_steps: int = 0, stream=None):
+                 back_pieces: int = 0, graph_steps: int = 0, stream=None,
+                 step_mode: int = 0):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("libtransims needs a GPU; none is visible")
@@ -185,7 +186,7 @@ class Context:
             stream = torch.cuda.current_stream()
         self.stream = stream
         cfg = sim_config(ABI_VERSION, max_slots, C.c_void_p(stream.cuda_stream),
-                         tile_lanes, back_pieces, graph_steps, 0)
+                         tile_lanes, back_pieces, graph_steps, step_mode)
         h = C.c_void_p()
         self._check(self.lib.sim_create(C.byref(cfg), C.byref(h)), None)
         self.h = h
@@ -276,10 +277,10 @@ class Context:
 
     def kernel_times(self) -> dict:
         """{kind: (launches, total_ms)} since the last call; waits."""
-        arr = (sim_kernel_time * 3)()
+        arr = (sim_kernel_time * 4)()
         self._check(self.lib.sim_kernel_times(self.h, arr))
         return {name: (arr[k].launches, arr[k].total_ms)
-                for k, name in enumerate(("front", "back", "ring"))}
+                for k, name in enumerate(("front", "back", "ring", "step"))}
 
     def unload(self, slot: int):
         self._check(self.lib.sim_unload(self.h, slot))

@@ -167,3 +167,40 @@ def test_dense_lanes_many_vehicle_groups(tile_lanes, pieces, flags):
         run_side_by_side(ctx, 0, scen, 120, every=20, full_at=(1, 60))
     finally:
         ctx.close()
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_step_modes_agree_with_oracle(mode):
+    # mode 0 runs this scenario (no lane changes, links >= 2 vmax cells) with
+    # one kernel per step, mode 1 with the lane-change and move kernels
+    from paper_cs_0105004_amd.sim import Context
+    scen = S.portland_like(scale=0.02, T=400)
+    assert scen.link_len.min() >= 2 * scen.vmax
+    ctx = Context(max_slots=1, step_mode=mode)
+    ctx.profile(True)
+    run_side_by_side(ctx, 0, scen, 400, every=40, full_at=(200,))
+    kt = ctx.kernel_times()
+    if mode == 0:
+        assert kt["step"][0] == 400 and kt["front"][0] == 0
+    else:
+        assert kt["step"][0] == 0 and kt["front"][0] == 400
+    ctx.close()
+
+
+def test_one_kernel_step_with_graphs_and_restart():
+    from paper_cs_0105004_amd.sim import Context
+    scen = S.portland_like(scale=0.05, T=600)
+    a = Context(max_slots=2, graph_steps=32)
+    a.load(0, scen)
+    a.step(0, 333)
+    mid = a.state(0)
+    a.step(0, 267)
+    o = oracle.OracleSim(scen)
+    o.step(600)
+    assert_same_stats(a.stats(0), o.stats(), "graphs")
+    assert_same_state(a.state(0), o.state(), "graphs")
+    # restart at an odd step: the parity buffers start from the other half
+    a.load(1, scen.with_state(mid, 333))
+    a.step(1, 267)
+    assert_same_state(a.state(1), o.state(), "restart at t=333")
+    a.close()
