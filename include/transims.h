@@ -46,7 +46,7 @@
 extern "C" {
 #endif
 
-#define SIM_ABI_VERSION 1
+#define SIM_ABI_VERSION 2
 
 typedef enum {
   SIM_OK = 0,
@@ -84,6 +84,10 @@ typedef struct {
                            cells, two kernels (lane-change / move sub-step)
                            otherwise; 1 = always two kernels.  Results are
                            the same either way.                             */
+  int32_t tile_cells;   /* one-kernel step: a tile also stops at this many
+                           cells (len x lanes; a longer link is a tile of
+                           its own), 64..65536; 0 = default (2048)          */
+  int32_t reserved;     /* must be 0                                        */
 } sim_config;
 
 /* Per-scenario parameters. */

@@ -656,6 +656,117 @@ __global__ __launch_bounds__(kWave) void k_back(
 }
 
 // ---------------------------------------------------------------------------
+// The move of one group of kGroup x 64 vehicles in the one-kernel step:
+// step_load reads what the group needs (vehicle records from the lanes'
+// rings, or from LDS for the vehicles that arrived in this step),
+// step_run updates the group.
+struct StepGroup {
+  v2u hw[kGroup];
+  v2i cw[kGroup];
+  uint32_t ahead[kGroup];
+  int sl[kGroup], lij[kGroup];
+};
+struct StepCtx {
+  int t, vmax;
+  uint32_t key0, key1;
+  uint64_t slow_thr;
+};
+
+__device__ __forceinline__ void step_load(
+    StepGroup& G, int g0, int i, int total, int nl, const int* s_pre,
+    const int* s_len, const int* s_base, const int* s_hp, const int* s_cnt0,
+    const uint2 (*s_nhot)[2], const int2 (*s_ncold)[2], GAS v2u* hot,
+    GAS uint32_t* hot_w, GAS v2i* cold) {
+#pragma unroll
+  for (int c = 0; c < kGroup; ++c) {
+    const int fr = (g0 + c) * kWave + i;
+    const int f = max(min(fr, total - 1), 0);
+    int lo = 0, hi = nl;
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (s_pre[mid] <= f) lo = mid;
+      else hi = mid;
+    }
+    const int j = f - s_pre[lo];
+    const int llen = s_len[lo], lbase = s_base[lo], lhp = s_hp[lo];
+    const int c0l = s_cnt0[lo];
+    G.sl[c] = rec_slot(lbase, lhp, llen, j);
+    // ring slots are loaded for every vehicle (an arrival's slot holds a
+    // stale record, replaced below), so no load sits in a branch
+    const int sa = j > 0 ? rec_slot(lbase, lhp, llen, j - 1) : G.sl[c];
+    const int sc = j <= 1 ? G.sl[c] : rec_slot(lbase, lhp, llen, 0);
+    G.hw[c] = hot[G.sl[c]];
+    G.ahead[c] = hot_w[2 * sa];
+    G.cw[c] = cold[sc];
+    if (j >= c0l) {  // an arrival of this step
+      const uint2 h = s_nhot[lo][j - c0l];
+      const int2 cc = s_ncold[lo][j - c0l];
+      G.hw[c] = (v2u){h.x, h.y};
+      G.cw[c] = (v2i){cc.x, cc.y};
+    }
+    if (j > 0 && j - 1 >= c0l) G.ahead[c] = s_nhot[lo][j - 1 - c0l].x;
+    G.lij[c] = (fr < total) ? (lo | (j << 8)) : -1;
+  }
+}
+
+__device__ __forceinline__ void step_run(
+    const StepGroup& G, const StepCtx& cx, const int* s_len, const int* s_cnt0,
+    const int* s_pre, const int* s_extra, const int* s_tgt, int4* s_ends,
+    int2* s_second, int* s_left, GAS v2u* hot, GAS uint32_t* hot_w,
+    GAS v2i* cold, const GAS uint32_t* __restrict__ route_info,
+    GAS int32_t* __restrict__ exit_t, GAS v4i* __restrict__ ha_out,
+    GAS int32_t* __restrict__ hb_out, unsigned long long& sumv,
+    unsigned long long& cross, unsigned long long& exits) {
+#pragma unroll
+  for (int c = 0; c < kGroup; ++c) {
+    if (G.lij[c] < 0) continue;
+    const int li = G.lij[c] & 0xFF, j = G.lij[c] >> 8;
+    const int llen = s_len[li];
+    const int x = xvf_x(G.hw[c].x), v = xvf_v(G.hw[c].x);
+    const uint32_t fl = xvf_fl(G.hw[c].x);
+    const int gap = j > 0 ? xvf_x(G.ahead[c]) - x - 1
+                          : llen - 1 - x + s_extra[li];
+    const int v1 = min(v + 1, cx.vmax);
+    const int v2 = min(v1, gap);
+    const uint32_t u = veh_draw(G.hw[c].y, (uint32_t)cx.t, 1u, cx.key0, cx.key1);
+    const int v3 = (v2 > 0 && (uint64_t)u < cx.slow_thr) ? v2 - 1 : v2;
+    const int nx = x + v3;
+    sumv += v3;
+    if (nx < llen) {
+      const uint32_t nw = pack_xvf(nx, v3, fl);
+      if (j >= s_cnt0[li]) {  // an arrival: its whole record
+        hot[G.sl[c]] = (v2u){nw, G.hw[c].y};
+        cold[G.sl[c]] = G.cw[c];
+      } else {
+        hot_w[2 * G.sl[c]] = nw;
+      }
+      const int lcnt = s_pre[li + 1] - s_pre[li];
+      if (j == 0) {
+        s_ends[li].x = (int)nw;
+        s_ends[li].y = G.cw[c].y;
+      } else if (j == 1) {
+        s_second[li] = make_int2((int)nw, G.cw[c].y);
+      }
+      if (j == lcnt - 1) s_ends[li].z = (int)nw;
+    } else {  // only a lead vehicle of the previous step passes the node
+      const int rp = G.cw[c].x;
+      exit_t[rp] = cx.t;
+      s_left[li] = 1;
+      if (fl & kFlLast) {
+        ++exits;
+      } else {
+        const uint32_t nfl = rinfo_flags((uint32_t)G.cw[c].y);
+        const int tg = s_tgt[li];
+        hb_out[tg] = (nfl & kFlLast) ? 0 : (int)route_info[rp + 2];
+        ha_out[tg] = (v4i){cx.t, (int)pack_xvf(nx - llen, v3, nfl),
+                           (int)G.hw[c].y, rp + 1};
+        ++cross;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // One kernel per step (see layout.h for when this is exact).  A wavefront
 // takes a tile, one lane per thread, and performs the whole step on it:
 //   1. merges the vehicle handed over to each lane in the previous step and
@@ -824,45 +935,18 @@ __global__ __launch_bounds__(kWave) void k_step(
       wave_sum((unsigned long long)(cntn > 0 ? len : 0));
   wave_lds_sync();
 
-  // 3. the move, groups of kGroup x 64 vehicles from the rear
+  // 3. the move, groups of kGroup x 64 vehicles from the rear: a group
+  // loads every record it needs before it rewrites any, so each vehicle
+  // reads the position of the one ahead before that one moves
   unsigned long long sumv = 0, cross = 0, exits = 0;
   const int nchunk = (total + kWave - 1) / kWave;
+  const StepCtx cx{t, vmax, key0, key1, slow_thr};
   bool first = true;
-  for (int g0 = ((nchunk - 1) / kGroup) * kGroup; g0 >= 0; g0 -= kGroup) {
-    v2u hw[kGroup];
-    v2i cw[kGroup];
-    uint32_t ahead[kGroup];
-    int sl[kGroup], lij[kGroup];
-#pragma unroll
-    for (int c = 0; c < kGroup; ++c) {
-      const int fr = (g0 + c) * kWave + i;
-      const int f = max(min(fr, total - 1), 0);
-      int lo = 0, hi = nl;
-      while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (s_pre[mid] <= f) lo = mid;
-        else hi = mid;
-      }
-      const int j = f - s_pre[lo];
-      const int llen = s_len[lo], lbase = s_base[lo], lhp = s_hp[lo];
-      const int c0l = s_cnt0[lo];
-      sl[c] = rec_slot(lbase, lhp, llen, j);
-      // ring slots are loaded for every vehicle (an arrival's slot holds a
-      // stale record, replaced below), so no load sits in a branch
-      const int sa = j > 0 ? rec_slot(lbase, lhp, llen, j - 1) : sl[c];
-      const int sc = j <= 1 ? sl[c] : rec_slot(lbase, lhp, llen, 0);
-      hw[c] = hot[sl[c]];
-      ahead[c] = hot_w[2 * sa];
-      cw[c] = cold[sc];
-      if (j >= c0l) {  // an arrival of this step
-        const uint2 h = s_nhot[lo][j - c0l];
-        const int2 cc = s_ncold[lo][j - c0l];
-        hw[c] = (v2u){h.x, h.y};
-        cw[c] = (v2i){cc.x, cc.y};
-      }
-      if (j > 0 && j - 1 >= c0l) ahead[c] = s_nhot[lo][j - 1 - c0l].x;
-      lij[c] = (fr < total) ? (lo | (j << 8)) : -1;
-    }
+  // (one pass with no vehicle still decides the winners)
+  for (int gr = ((nchunk - 1) / kGroup) * kGroup; gr >= 0; gr -= kGroup) {
+    StepGroup G;
+    step_load(G, gr, i, total, nl, s_pre, s_len, s_base, s_hp, s_cnt0, s_nhot,
+              s_ncold, hot, hot_w, cold);
     if (first) {
       // winners: extra cells past the link end (rule R7); the claim is
       // cleared for the next use of this buffer
@@ -882,61 +966,17 @@ __global__ __launch_bounds__(kWave) void k_step(
                                           : vmax;
             if (m < tlanes && (!has || rx[m] != 0)) free_m |= 1u << m;
           }
-          const bool tins = tqn <= t && free_m != 0 &&
-                            __builtin_ctz(free_m) == tm;
+          const bool tins =
+              tqn <= t && free_m != 0 && __builtin_ctz(free_m) == tm;
           extra = tins ? 0 : min(vmax, rx[tm]);
         }
         s_extra[i] = extra;
       }
       wave_lds_sync();
     }
-#pragma unroll
-    for (int c = 0; c < kGroup; ++c) {
-      if (lij[c] < 0) continue;
-      const int li = lij[c] & 0xFF, j = lij[c] >> 8;
-      const int llen = s_len[li];
-      const int x = xvf_x(hw[c].x), v = xvf_v(hw[c].x);
-      const uint32_t fl = xvf_fl(hw[c].x);
-      const int gap = j > 0 ? xvf_x(ahead[c]) - x - 1
-                            : llen - 1 - x + s_extra[li];
-      const int v1 = min(v + 1, vmax);
-      const int v2 = min(v1, gap);
-      const uint32_t u = veh_draw(hw[c].y, (uint32_t)t, 1u, key0, key1);
-      const int v3 = (v2 > 0 && (uint64_t)u < slow_thr) ? v2 - 1 : v2;
-      const int nx = x + v3;
-      sumv += v3;
-      if (nx < llen) {
-        const uint32_t nw = pack_xvf(nx, v3, fl);
-        if (j >= s_cnt0[li]) {  // an arrival: its whole record
-          hot[sl[c]] = (v2u){nw, hw[c].y};
-          cold[sl[c]] = cw[c];
-        } else {
-          hot_w[2 * sl[c]] = nw;
-        }
-        const int lcnt = s_pre[li + 1] - s_pre[li];
-        if (j == 0) {
-          s_ends[li].x = (int)nw;
-          s_ends[li].y = cw[c].y;
-        } else if (j == 1) {
-          s_second[li] = make_int2((int)nw, cw[c].y);
-        }
-        if (j == lcnt - 1) s_ends[li].z = (int)nw;
-      } else {  // only a lead vehicle of the previous step passes the node
-        const int rp = cw[c].x;
-        exit_t[rp] = t;
-        s_left[li] = 1;
-        if (fl & kFlLast) {
-          ++exits;
-        } else {
-          const uint32_t nfl = rinfo_flags((uint32_t)cw[c].y);
-          const int tg = s_tgt[li];
-          hb_out[tg] = (nfl & kFlLast) ? 0 : (int)route_info[rp + 2];
-          ha_out[tg] = (v4i){t, (int)pack_xvf(nx - llen, v3, nfl),
-                             (int)hw[c].y, rp + 1};
-          ++cross;
-        }
-      }
-    }
+    step_run(G, cx, s_len, s_cnt0, s_pre, s_extra, s_tgt, s_ends, s_second,
+             s_left, hot, hot_w, cold, route_info, exit_t, ha_out, hb_out,
+             sumv, cross, exits);
   }
   wave_lds_sync();
 

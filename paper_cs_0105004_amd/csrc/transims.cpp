@@ -27,7 +27,7 @@ constexpr int kDefaultBackPieces = 4;
 constexpr int kDefaultGraphSteps = 64;
 // one-kernel steps: a tile also stops at this many cells, so that no
 // wavefront is left with a much longer queue of vehicles than the rest
-constexpr int kFusedTileCells = 1024;
+constexpr int kDefaultTileCells = 2048;
 
 struct Slot {
   bool net = false, veh = false, ring = false;
@@ -277,12 +277,16 @@ extern "C" sim_status sim_create(const sim_config* cfg, sim_ctx** out) {
   if (cfg->tile_lanes < 0 || cfg->tile_lanes > kMaxTileLanes) return SIM_E_INVAL;
   if (cfg->back_pieces < 0 || cfg->back_pieces > 8) return SIM_E_INVAL;
   if (cfg->step_mode < 0 || cfg->step_mode > 1) return SIM_E_INVAL;
+  if (cfg->tile_cells != 0 && (cfg->tile_cells < 64 || cfg->tile_cells > 65536))
+    return SIM_E_INVAL;
+  if (cfg->reserved != 0) return SIM_E_INVAL;
   sim_ctx* c = new (std::nothrow) sim_ctx();
   if (!c) return SIM_E_CAPACITY;
   c->cfg = *cfg;
   if (c->cfg.tile_lanes == 0) c->cfg.tile_lanes = kDefaultTileLanes;
   if (c->cfg.back_pieces == 0) c->cfg.back_pieces = kDefaultBackPieces;
   if (c->cfg.graph_steps == 0) c->cfg.graph_steps = kDefaultGraphSteps;
+  if (c->cfg.tile_cells == 0) c->cfg.tile_cells = kDefaultTileCells;
   c->stream = reinterpret_cast<hipStream_t>(cfg->stream);
   c->slots.resize(cfg->max_slots);
   if (hipGetDevice(&c->device) != hipSuccess ||
@@ -397,7 +401,7 @@ extern "C" sim_status sim_load_network(sim_ctx* c, int32_t slot,
     S.fused = !S.ring && c->cfg.step_mode == 0 &&
               !(p->flags & SIM_FLAG_LANE_CHANGE) && min_len >= 2 * p->vmax;
   }
-  S.ftiles = S.fused ? pack_tiles(S.lanes, S.len, c->cfg.tile_lanes, kFusedTileCells)
+  S.ftiles = S.fused ? pack_tiles(S.lanes, S.len, c->cfg.tile_lanes, c->cfg.tile_cells)
                      : pack_tiles(S.lanes, c->cfg.tile_lanes);
   S.n_ftiles = (int32_t)S.ftiles.size();
   S.tiles = S.ftiles;  // the move sub-step splits these tiles further

@@ -17,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libtransims.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "transims.h")
 
-ABI_VERSION = 1
+ABI_VERSION = 2
 OK, E_INVAL, E_NOMEM, E_STATE, E_DEVICE, E_CAPACITY, E_ABI = 0, -1, -2, -3, -4, -5, -6
 STATUS_NAMES = {0: "SIM_OK", -1: "SIM_E_INVAL", -2: "SIM_E_NOMEM",
                 -3: "SIM_E_STATE", -4: "SIM_E_DEVICE", -5: "SIM_E_CAPACITY",
@@ -34,7 +34,8 @@ class sim_config(C.Structure):
     _fields_ = [("abi_version", C.c_int32), ("max_slots", C.c_int32),
                 ("stream", C.c_void_p), ("tile_lanes", C.c_int32),
                 ("back_pieces", C.c_int32), ("graph_steps", C.c_int32),
-                ("step_mode", C.c_int32)]
+                ("step_mode", C.c_int32), ("tile_cells", C.c_int32),
+                ("reserved", C.c_int32)]
 
 
 class sim_params(C.Structure):
@@ -176,7 +177,7 @@ class Context:
 
     def __init__(self, max_slots: int = 1, tile_lanes: int = 0,
                  back_pieces: int = 0, graph_steps: int = 0, stream=None,
-                 step_mode: int = 0):
+                 step_mode: int = 0, tile_cells: int = 0):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("libtransims needs a GPU; none is visible")
@@ -186,7 +187,8 @@ class Context:
             stream = torch.cuda.current_stream()
         self.stream = stream
         cfg = sim_config(ABI_VERSION, max_slots, C.c_void_p(stream.cuda_stream),
-                         tile_lanes, back_pieces, graph_steps, step_mode)
+                         tile_lanes, back_pieces, graph_steps, step_mode,
+                         tile_cells, 0)
         h = C.c_void_p()
         self._check(self.lib.sim_create(C.byref(cfg), C.byref(h)), None)
         self.h = h

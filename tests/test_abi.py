@@ -55,7 +55,7 @@ def test_no_gpu_no_fallback():
 
 def test_struct_layouts_match_header():
     import ctypes as C
-    assert C.sizeof(sim.sim_config) == 32
+    assert C.sizeof(sim.sim_config) == 40
     assert C.sizeof(sim.sim_params) == 40
     assert C.sizeof(sim.sim_stats_t) == 8 + 10 * 8 + 8 + 8
     assert C.sizeof(sim.sim_tiling) == 32

@@ -55,11 +55,16 @@ def test_batched_equals_plain_loop(small_batch):
 def test_autotune_returns_a_consistent_choice(small_batch):
     from paper_cs_0105004_amd.autotune import autotune
     best = autotune(small_batch[:4], warm_steps=50, trial_steps=16, reps=1,
-                    tile_lanes=(8, 32), graph_steps=(16, 64))
+                    tile_lanes=(8, 32), graph_steps=(16, 64),
+                    tile_cells=(256, 2048))
     assert best["tile_lanes"] in (8, 32) and best["graph_steps"] in (16, 64)
-    assert len(best["trials"]) == 3  # 2 tile sizes, then 1 new graph size
+    assert best["tile_cells"] in (256, 2048)
+    # 2 tile sizes (at the default cell cap, 2048), then the other cell cap,
+    # then the one graph length not tried yet
+    assert len(best["trials"]) == 4
     assert best["us_per_step"] == min(t["us_per_step"] for t in best["trials"]
                                       if t["tile_lanes"] == best["tile_lanes"]
+                                      and t["tile_cells"] == best["tile_cells"]
                                       and t["graph_steps"] == best["graph_steps"])
     single = autotune(small_batch[:1], warm_steps=20, trial_steps=8, reps=1,
                       tile_lanes=(16,), back_pieces=(1, 4), graph_steps=(8,))
