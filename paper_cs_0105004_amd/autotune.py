@@ -17,7 +17,7 @@ import time
 from typing import Dict, List, Sequence
 
 TILE_LANES = (8, 16, 32, 64)
-TILE_CELLS = (512, 1024, 2048, 4096)
+TILE_CELLS = (1024, 2048, 4096, 8192, 16384)
 BACK_PIECES = (1, 2, 4, 8)
 GRAPH_STEPS = (32, 64, 128)
 
@@ -100,13 +100,18 @@ def autotune(scens: Sequence, warm_steps: int = 600, trial_steps: int = 128,
     if single and two:
         knobs.append(("back_pieces", back_pieces))
     knobs.append(("graph_steps", graph_steps))
-    for name, values in knobs:
-        best = None
-        for v in values:
-            r = run({**cur, name: int(v)})
-            if best is None or r["us_per_step"] < best["us_per_step"]:
-                best = r
-        cur[name] = best[name]
+    # coordinate descent, repeated while a pass still moves (at most 3)
+    for _ in range(3):
+        before = dict(cur)
+        for name, values in knobs:
+            best = None
+            for v in values:
+                r = run({**cur, name: int(v)})
+                if best is None or r["us_per_step"] < best["us_per_step"]:
+                    best = r
+            cur[name] = best[name]
+        if cur == before:
+            break
     final = seen[(cur["tile_lanes"], cur["tile_cells"], cur["back_pieces"],
                   cur["graph_steps"])]
     return {**cur, "us_per_step": final["us_per_step"],

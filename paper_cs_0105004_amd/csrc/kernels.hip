@@ -674,8 +674,7 @@ struct StepCtx {
 
 __device__ __forceinline__ void step_load(
     StepGroup& G, int g0, int i, int total, int nl, const int* s_pre,
-    const int* s_len, const int* s_base, const int* s_hp, const int* s_cnt0,
-    const uint2 (*s_nhot)[2], const int2 (*s_ncold)[2], GAS v2u* hot,
+    const int* s_len, const int* s_base, const int* s_hp, GAS v2u* hot,
     GAS uint32_t* hot_w, GAS v2i* cold) {
 #pragma unroll
   for (int c = 0; c < kGroup; ++c) {
@@ -689,77 +688,83 @@ __device__ __forceinline__ void step_load(
     }
     const int j = f - s_pre[lo];
     const int llen = s_len[lo], lbase = s_base[lo], lhp = s_hp[lo];
-    const int c0l = s_cnt0[lo];
     G.sl[c] = rec_slot(lbase, lhp, llen, j);
     // ring slots are loaded for every vehicle (an arrival's slot holds a
-    // stale record, replaced below), so no load sits in a branch
+    // stale record, which step_run replaces from LDS), so no load sits in
+    // a branch
     const int sa = j > 0 ? rec_slot(lbase, lhp, llen, j - 1) : G.sl[c];
     const int sc = j <= 1 ? G.sl[c] : rec_slot(lbase, lhp, llen, 0);
     G.hw[c] = hot[G.sl[c]];
     G.ahead[c] = hot_w[2 * sa];
     G.cw[c] = cold[sc];
-    if (j >= c0l) {  // an arrival of this step
-      const uint2 h = s_nhot[lo][j - c0l];
-      const int2 cc = s_ncold[lo][j - c0l];
-      G.hw[c] = (v2u){h.x, h.y};
-      G.cw[c] = (v2i){cc.x, cc.y};
-    }
-    if (j > 0 && j - 1 >= c0l) G.ahead[c] = s_nhot[lo][j - 1 - c0l].x;
     G.lij[c] = (fr < total) ? (lo | (j << 8)) : -1;
   }
 }
 
 __device__ __forceinline__ void step_run(
     const StepGroup& G, const StepCtx& cx, const int* s_len, const int* s_cnt0,
-    const int* s_pre, const int* s_extra, const int* s_tgt, int4* s_ends,
+    const int* s_pre, const int* s_extra, const int* s_tgt,
+    const uint2 (*s_nhot)[2], const int2 (*s_ncold)[2], int4* s_ends,
     int2* s_second, int* s_left, GAS v2u* hot, GAS uint32_t* hot_w,
     GAS v2i* cold, const GAS uint32_t* __restrict__ route_info,
     GAS int32_t* __restrict__ exit_t, GAS v4i* __restrict__ ha_out,
-    GAS int32_t* __restrict__ hb_out, unsigned long long& sumv,
-    unsigned long long& cross, unsigned long long& exits) {
+    GAS int32_t* __restrict__ hb_out, GAS int32_t* __restrict__ ht_out,
+    unsigned long long& sumv, unsigned long long& cross,
+    unsigned long long& exits) {
 #pragma unroll
   for (int c = 0; c < kGroup; ++c) {
     if (G.lij[c] < 0) continue;
     const int li = G.lij[c] & 0xFF, j = G.lij[c] >> 8;
     const int llen = s_len[li];
-    const int x = xvf_x(G.hw[c].x), v = xvf_v(G.hw[c].x);
-    const uint32_t fl = xvf_fl(G.hw[c].x);
-    const int gap = j > 0 ? xvf_x(G.ahead[c]) - x - 1
-                          : llen - 1 - x + s_extra[li];
+    const int c0l = s_cnt0[li];
+    v2u hw = G.hw[c];
+    v2i cw = G.cw[c];
+    uint32_t ahead = G.ahead[c];
+    if (j >= c0l) {  // an arrival of this step
+      const uint2 h = s_nhot[li][j - c0l];
+      const int2 cc = s_ncold[li][j - c0l];
+      hw = (v2u){h.x, h.y};
+      cw = (v2i){cc.x, cc.y};
+    }
+    if (j > 0 && j - 1 >= c0l) ahead = s_nhot[li][j - 1 - c0l].x;
+    const int x = xvf_x(hw.x), v = xvf_v(hw.x);
+    const uint32_t fl = xvf_fl(hw.x);
+    const int gap = j > 0 ? xvf_x(ahead) - x - 1 : llen - 1 - x + s_extra[li];
     const int v1 = min(v + 1, cx.vmax);
     const int v2 = min(v1, gap);
-    const uint32_t u = veh_draw(G.hw[c].y, (uint32_t)cx.t, 1u, cx.key0, cx.key1);
+    const uint32_t u = veh_draw(hw.y, (uint32_t)cx.t, 1u, cx.key0, cx.key1);
     const int v3 = (v2 > 0 && (uint64_t)u < cx.slow_thr) ? v2 - 1 : v2;
     const int nx = x + v3;
     sumv += v3;
     if (nx < llen) {
       const uint32_t nw = pack_xvf(nx, v3, fl);
-      if (j >= s_cnt0[li]) {  // an arrival: its whole record
-        hot[G.sl[c]] = (v2u){nw, G.hw[c].y};
-        cold[G.sl[c]] = G.cw[c];
+      if (j >= c0l) {  // an arrival: its whole record
+        hot[G.sl[c]] = (v2u){nw, hw.y};
+        cold[G.sl[c]] = cw;
       } else {
         hot_w[2 * G.sl[c]] = nw;
       }
       const int lcnt = s_pre[li + 1] - s_pre[li];
       if (j == 0) {
         s_ends[li].x = (int)nw;
-        s_ends[li].y = G.cw[c].y;
+        s_ends[li].y = cw.y;
       } else if (j == 1) {
-        s_second[li] = make_int2((int)nw, G.cw[c].y);
+        s_second[li] = make_int2((int)nw, cw.y);
       }
       if (j == lcnt - 1) s_ends[li].z = (int)nw;
     } else {  // only a lead vehicle of the previous step passes the node
-      const int rp = G.cw[c].x;
+      const int rp = cw.x;
       exit_t[rp] = cx.t;
       s_left[li] = 1;
       if (fl & kFlLast) {
         ++exits;
       } else {
-        const uint32_t nfl = rinfo_flags((uint32_t)G.cw[c].y);
+        const uint32_t nfl = rinfo_flags((uint32_t)cw.y);
         const int tg = s_tgt[li];
         hb_out[tg] = (nfl & kFlLast) ? 0 : (int)route_info[rp + 2];
         ha_out[tg] = (v4i){cx.t, (int)pack_xvf(nx - llen, v3, nfl),
-                           (int)G.hw[c].y, rp + 1};
+                           (int)hw.y, rp + 1};
+        ht_out[tg] = (cx.t << 1) | (nx == llen ? 1 : 0);
         ++cross;
       }
     }
@@ -801,7 +806,6 @@ __global__ __launch_bounds__(kWave) void k_step(
   const int vmax = S.vmax;
   const uint32_t key0 = S.key0, key1 = S.key1;
   const uint64_t slow_thr = S.slow_thr;
-  const GAS v4i* __restrict__ lane_info = gpv<v4i>(S.lane_info);
   const GAS v4i* __restrict__ ls_cur = gpv<v4i>(S.lane_state + p * Q);
   GAS v4i* __restrict__ ls_nxt = gpv<v4i>(S.lane_state + (p ^ 1) * Q);
   const GAS v4i* __restrict__ ha_in = gpv<v4i>(S.hand_a + (p ^ 1) * Q);
@@ -812,6 +816,10 @@ __global__ __launch_bounds__(kWave) void k_step(
   GAS int32_t* __restrict__ cl_nxt = gp(S.claim + (p ^ 1) * Q);
   const GAS int32_t* __restrict__ qn_cur = gp(S.qnext + p * Q);
   GAS int32_t* __restrict__ qn_nxt = gp(S.qnext + (p ^ 1) * Q);
+  const GAS int32_t* __restrict__ ht_in = gp(S.hand_tag + (p ^ 1) * Q);
+  const GAS v2i* __restrict__ lane_bm = gpv<v2i>(S.lane_bm);
+  const GAS int32_t* __restrict__ lane_qend = gp(S.lane_qend);
+  GAS int32_t* __restrict__ ht_out = gp(S.hand_tag + p * Q);
   GAS int32_t* __restrict__ lane_qhead = gp(S.lane_qhead);
   GAS v4i* __restrict__ lane_qrec = gpv<v4i>(S.lane_qrec);
   const GAS v4i* __restrict__ wait_rec = gpv<v4i>(S.wait_rec);
@@ -826,65 +834,65 @@ __global__ __launch_bounds__(kWave) void k_step(
   const bool act = i < nl;
   const int g = w.y + i;
 
-  // 1. everything of the lane from the previous step, in one round
-  v4i info = {0, 0, 0, 0}, st = {0, 0, 0, 0}, ha = {kTagNone, 0, 0, 0};
-  v4i qrec = {-1, 0, 0, 0};
-  int hb = 0, qh = 0, qn = INT32_MAX;
+  // 1. what every lane needs from the previous step, in one round: its
+  // static word, its state, the tag of the last handoff into it and (lane
+  // 0) the departure time of its link's queue head
+  v2i bm = {0, 0};
+  v4i st = {0, 0, 0, 0};
+  int htag = kTagNone, qn = INT32_MAX;
   if (act) {
-    info = lane_info[g];
+    bm = lane_bm[g];
     st = ls_cur[g];
-    ha = ha_in[g];
-    hb = hb_in[g];
-    qh = lane_qhead[g];
-    qrec = lane_qrec[g];
+    htag = ht_in[g];
     qn = qn_cur[g];
   }
-  const uint32_t meta = (uint32_t)info.y;
+  const uint32_t meta = (uint32_t)bm.y;
   const int len = act ? lmeta_len(meta) : 1;
   const int k = lmeta_k(meta), lanes = lmeta_lanes(meta);
   const int key = lmeta_rank(meta) * 8 + k;
   const int head = hc_head(st.w);
   const int cnt = act ? hc_cnt(st.w) : 0;
   const uint32_t lead_w = (uint32_t)st.x;
-  int n_new = 0;
-  uint32_t rear_w = (uint32_t)st.z;
-  if (act && ha.x == t - 1) {
-    if (cnt >= len) {
-      atomicOr(S.err, SIM_DEVERR_LANE_FULL);
-    } else {
-      s_nhot[i][0] = make_uint2((uint32_t)ha.y, (uint32_t)ha.z);
-      s_ncold[i][0] = make_int2(ha.w, hb);
-      rear_w = (uint32_t)ha.y;
-      n_new = 1;
-    }
+  // a vehicle handed over in the previous step joins at the rear (its
+  // record is read below); the tag says whether it landed on cell 0
+  bool arr = false;
+  if (act && (htag >> 1) == t - 1) {
+    if (cnt >= len) atomicOr(S.err, SIM_DEVERR_LANE_FULL);
+    else arr = true;
   }
-  const bool empty0 = act && ((cnt + n_new) == 0 || xvf_x(rear_w) != 0);
+  const int rear_x =
+      arr ? ((htag & 1) ? 0 : 1) : (cnt > 0 ? xvf_x((uint32_t)st.z) : 1);
+  const bool empty0 = act && rear_x != 0;
   const unsigned long long free0 = __ballot(empty0);
   const int l0 = i - k;  // this link's lane 0 in the tile
-  const int qid = __shfl(qrec.x, l0), qdep = __shfl(qrec.y, l0),
-            qrp = __shfl(qrec.z, l0), qni = __shfl(qrec.w, l0);
   const int qn0 = __shfl(qn, l0);
   int ins = 0;
   if (empty0) {
     const unsigned long long lm = (free0 >> l0) & ((1ull << lanes) - 1ull);
-    if (__builtin_ctzll(lm) == k && qn0 <= t) {
-      s_nhot[i][n_new] =
-          make_uint2(pack_xvf(0, 0, (uint32_t)qdep >> kDepartBits), (uint32_t)qid);
-      s_ncold[i][n_new] = make_int2(qrp, qni);
-      ++n_new;
-      ins = 1;
-    }
+    if (__builtin_ctzll(lm) == k && qn0 <= t) ins = 1;
   }
   const unsigned long long insm = __ballot(ins);
   const bool link_ins =
       act && k == 0 && ((insm >> i) & ((1ull << lanes) - 1ull)) != 0;
-  // the link's next queue head, for the next step
-  v4i nrec = {-1, 0, 0, 0};
-  if (link_ins && qh + 1 < info.w) nrec = wait_rec[qh + 1];
+  const int n_new = (arr ? 1 : 0) + ins;
+  // second round, only where something arrives: the handed-over record,
+  // and the head of the parking queue (read by lane 0, which also
+  // prefetches the next head for the next step)
+  v4i ha = {0, 0, 0, 0}, qrec = {0, 0, 0, 0}, nrec = {-1, 0, 0, 0};
+  int hb = 0, qh = 0, qend = 0;
+  if (arr) {
+    ha = ha_in[g];
+    hb = hb_in[g];
+  }
+  if (link_ins) {
+    qh = lane_qhead[g];
+    qrec = lane_qrec[g];
+    qend = lane_qend[g];
+  }
 
-  // 2. the lead vehicle at the node: target lane, its claim, and the state
-  // of the target link's lanes (loaded by every candidate, used by the
-  // winner)
+  // 2. the lead vehicle at the node: target lane, its claim, and the
+  // arrivals of the target link's lanes (read by every candidate, used by
+  // the winner)
   const bool cand = act && cnt > 0 && len - 1 - xvf_x(lead_w) < vmax;
   const bool exits_here = cand && (xvf_fl(lead_w) & kFlLast);
   int tgt = exits_here ? -2 : -1, tm = 0, tlanes = 1, tl0 = 0;
@@ -913,7 +921,7 @@ __global__ __launch_bounds__(kWave) void k_step(
     }
   }
   if (act) {
-    s_base[i] = info.x;
+    s_base[i] = bm.x;
     s_hp[i] = hc_make(head, 0, 0);
     s_len[i] = len;
     s_cnt0[i] = cnt;
@@ -945,12 +953,26 @@ __global__ __launch_bounds__(kWave) void k_step(
   // (one pass with no vehicle still decides the winners)
   for (int gr = ((nchunk - 1) / kGroup) * kGroup; gr >= 0; gr -= kGroup) {
     StepGroup G;
-    step_load(G, gr, i, total, nl, s_pre, s_len, s_base, s_hp, s_cnt0, s_nhot,
-              s_ncold, hot, hot_w, cold);
+    step_load(G, gr, i, total, nl, s_pre, s_len, s_base, s_hp, hot, hot_w,
+              cold);
     if (first) {
+      first = false;
+      // the arrivals' records go to LDS; the inserting lane takes the queue
+      // head that lane 0 of its link read
+      const int qid = __shfl(qrec.x, l0), qdep = __shfl(qrec.y, l0),
+                qrp = __shfl(qrec.z, l0), qni = __shfl(qrec.w, l0);
+      if (arr) {
+        s_nhot[i][0] = make_uint2((uint32_t)ha.y, (uint32_t)ha.z);
+        s_ncold[i][0] = make_int2(ha.w, hb);
+      }
+      if (ins) {
+        s_nhot[i][arr ? 1 : 0] = make_uint2(
+            pack_xvf(0, 0, (uint32_t)qdep >> kDepartBits), (uint32_t)qid);
+        s_ncold[i][arr ? 1 : 0] = make_int2(qrp, qni);
+      }
+      if (link_ins && qh + 1 < qend) nrec = wait_rec[qh + 1];
       // winners: extra cells past the link end (rule R7); the claim is
       // cleared for the next use of this buffer
-      first = false;
       if (act) {
         int extra = exits_here ? vmax : 0;
         if (tgt >= 0 && claim == key) {
@@ -960,11 +982,10 @@ __global__ __launch_bounds__(kWave) void k_step(
           unsigned free_m = 0;
 #pragma unroll
           for (int m = 0; m < 4; ++m) {
-            const bool has = tpend[m] != kTagNone || tcnt[m] > 0;
             rx[m] = tpend[m] != kTagNone ? xvf_x((uint32_t)tpend[m])
                     : tcnt[m] > 0         ? xvf_x((uint32_t)trear[m])
                                           : vmax;
-            if (m < tlanes && (!has || rx[m] != 0)) free_m |= 1u << m;
+            if (m < tlanes && rx[m] != 0) free_m |= 1u << m;
           }
           const bool tins =
               tqn <= t && free_m != 0 && __builtin_ctz(free_m) == tm;
@@ -974,9 +995,9 @@ __global__ __launch_bounds__(kWave) void k_step(
       }
       wave_lds_sync();
     }
-    step_run(G, cx, s_len, s_cnt0, s_pre, s_extra, s_tgt, s_ends, s_second,
-             s_left, hot, hot_w, cold, route_info, exit_t, ha_out, hb_out,
-             sumv, cross, exits);
+    step_run(G, cx, s_len, s_cnt0, s_pre, s_extra, s_tgt, s_nhot, s_ncold,
+             s_ends, s_second, s_left, hot, hot_w, cold, route_info, exit_t,
+             ha_out, hb_out, ht_out, sumv, cross, exits);
   }
   wave_lds_sync();
 
@@ -1002,8 +1023,8 @@ __global__ __launch_bounds__(kWave) void k_step(
       if (link_ins) {
         lane_qhead[g] = qh + 1;
         lane_qrec[g] = nrec;
-        qn_nxt[g] = qh + 1 < info.w ? (nrec.y & ((1 << kDepartBits) - 1))
-                                    : INT32_MAX;
+        qn_nxt[g] = qh + 1 < qend ? (nrec.y & ((1 << kDepartBits) - 1))
+                                  : INT32_MAX;
       } else {
         qn_nxt[g] = qn;
       }

@@ -149,6 +149,14 @@ struct DevScen {
   int4* lane_qrec;
   // fused: depart of the link's queue head (INT32_MAX: empty), at lane 0
   int32_t* qnext;
+  // fused: what the one-kernel step reads of every lane, kept small --
+  //   lane_bm {record base, lmeta}; hand_tag[2][n_lanes] = t << 1 | (landed
+  //   on cell 0) of the last vehicle handed over to the lane in a step of
+  //   that parity (its record is in hand_a / hand_b); lane_qend at lane 0:
+  //   end of the link's parking queue in wait_rec
+  const int2* lane_bm;
+  int32_t* hand_tag;
+  const int32_t* lane_qend;
   // vehicle records
   uint2* hot;
   int2* cold;

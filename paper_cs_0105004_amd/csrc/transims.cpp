@@ -148,6 +148,9 @@ void carve_network(Carve& cv, const NetDims& nd, DevScen& d, bool ring) {
   d.hand_a = cv.take<int4>(2 * Q);
   d.hand_b = cv.take<int32_t>(2 * Q);
   d.qnext = cv.take<int32_t>(2 * Q);
+  d.lane_bm = cv.take<int2>(Q);
+  d.lane_qend = cv.take<int32_t>(Q);
+  d.hand_tag = cv.take<int32_t>(2 * Q);
   d.lane_qhead = cv.take<int32_t>(Q);
   d.lane_qrec = cv.take<int4>(Q);
   d.hot = cv.take<uint2>(ring ? 0 : nd.rec);
@@ -473,6 +476,12 @@ extern "C" sim_status sim_load_network(sim_ctx* c, int32_t slot,
   hipStream_t s = c->stream;
   HIPCHK(c, up(const_cast<int32_t*>(d.link_ext), S.ext_of.data(), L, s));
   HIPCHK(c, up(const_cast<int4*>(d.lane_info), lane_info.data(), S.n_lanes, s));
+  {
+    std::vector<int2> bm(S.n_lanes);
+    for (int32_t qq = 0; qq < S.n_lanes; ++qq)
+      bm[qq] = make_int2(lane_info[qq].x, lane_info[qq].y);
+    HIPCHK(c, up(const_cast<int2*>(d.lane_bm), bm.data(), S.n_lanes, s));
+  }
   HIPCHK(c, hipStreamSynchronize(s));
   S.net = true;
   c->work_key.clear();  // slot contents changed: rebuild work lists
@@ -501,6 +510,8 @@ extern "C" sim_status sim_load_vehicles(sim_ctx* c, int32_t slot,
     std::vector<int4> hand_a(2 * S.n_lanes, make_int4(kTagNone, 0, 0, 0));
     HIPCHK(c, up(d.hand_a, hand_a.data(), 2 * S.n_lanes, s));
     HIPCHK(c, hipMemsetAsync(d.lane_state, 0, sizeof(int4) * 2 * S.n_lanes, s));
+    std::vector<int32_t> tags(2 * S.n_lanes, kTagNone);
+    HIPCHK(c, up(d.hand_tag, tags.data(), 2 * S.n_lanes, s));
     HIPCHK(c, hipMemsetAsync(d.tile_ctr, 0, sizeof(long long) * C_N * S.n_lanes, s));
     HIPCHK(c, hipMemsetAsync(d.ftile_ctr, 0, sizeof(long long) * C_N * S.n_ftiles, s));
     HIPCHK(c, hipMemsetAsync(d.xcount, 0, sizeof(int32_t) * 2, s));
@@ -696,6 +707,11 @@ extern "C" sim_status sim_load_vehicles(sim_ctx* c, int32_t slot,
     HIPCHK(c, up(d.lane_qhead, qhead.data(), S.n_lanes, s));
     HIPCHK(c, up(d.lane_qrec, qrec.data(), S.n_lanes, s));
     HIPCHK(c, up(const_cast<int4*>(d.lane_info), S.lane_info.data(), S.n_lanes, s));
+    {
+      std::vector<int32_t> qend(S.n_lanes);
+      for (int32_t qq = 0; qq < S.n_lanes; ++qq) qend[qq] = S.lane_info[qq].w;
+      HIPCHK(c, up(const_cast<int32_t*>(d.lane_qend), qend.data(), S.n_lanes, s));
+    }
     HIPCHK(c, up(const_cast<int64_t*>(d.route_off), v->route_off, n + 1, s));
     HIPCHK(c, up(const_cast<uint32_t*>(d.route_info), rinfo.data(), R, s));
     HIPCHK(c, up(d.exit_t, exit_t.data(), R, s));
@@ -980,6 +996,8 @@ extern "C" sim_status sim_step(sim_ctx* c, const int32_t* slots, int32_t n_slots
     if (seen[slots[k]]++) return fail(c, SIM_E_INVAL, "slot %d listed twice", slots[k]);
     if ((int64_t)S.t + n_steps > INT32_MAX - 1)
       return fail(c, SIM_E_CAPACITY, "step index would overflow");
+    if (S.fused && (int64_t)S.t + n_steps >= (int64_t)1 << 30)
+      return fail(c, SIM_E_CAPACITY, "one-kernel steps stop at t = 2^30");
     (S.ring ? ring : net).push_back(slots[k]);
   }
   if (n_steps == 0) return SIM_OK;

@@ -31,11 +31,18 @@ def test_portland_full_run_matches_oracle(portland):
     ctx.close()
 
 
-@pytest.mark.parametrize("pieces,graph", [(1, -1), (8, 200)])
-def test_portland_configs_agree(portland, pieces, graph):
+# Launch configurations that change the number of workgroups by 40x: with
+# tiles of one lane, many more workgroups run than fit on the device at once,
+# so a tile may run long after the tiles it reads from -- every read of
+# another tile's data must see the previous step's values regardless.
+@pytest.mark.parametrize("mode,lanes,cells,pieces,graph", [
+    (1, 16, 0, 1, -1), (1, 16, 0, 8, 200), (1, 1, 0, 1, 64),
+    (0, 1, 0, 1, 64), (0, 4, 256, 1, 32), (0, 64, 65536, 1, 64)])
+def test_portland_configs_agree(portland, mode, lanes, cells, pieces, graph):
     from paper_cs_0105004_amd.sim import Context
     ref = Context(max_slots=1)
-    alt = Context(max_slots=1, back_pieces=pieces, graph_steps=graph)
+    alt = Context(max_slots=1, step_mode=mode, tile_lanes=lanes,
+                  tile_cells=cells, back_pieces=pieces, graph_steps=graph)
     ref.load(0, portland)
     alt.load(0, portland)
     ref.step(0, 1500)
