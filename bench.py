@@ -43,6 +43,15 @@ def make_workload(name: str, steps: int):
                "nodes": scen.n_nodes, "lanes": int(scen.link_lanes.sum()),
                "vehicles": scen.n_veh, "horizon_steps": steps, "vmax": 5,
                "p": 0.2, "lane_change": False}
+    elif name == "portland_signals":
+        scen = S.portland_like(T=steps, signals=(60, 30))
+        cfg = {"workload": "portland_like_grid_signals", "links": scen.n_links,
+               "nodes": scen.n_nodes, "lanes": int(scen.link_lanes.sum()),
+               "vehicles": scen.n_veh, "horizon_steps": steps, "vmax": 5,
+               "p": 0.2, "lane_change": False,
+               "signals": "cycle 60 s, red 30 s, E-W / N-S phases, "
+                          "nodes with >= 3 approaches",
+               "signalised_links": int((scen.signal_plan >= 0).sum())}
     elif name == "large":
         scen = S.large_network(T=steps)
         cfg = {"workload": "large_grid_200k_links", "links": scen.n_links,

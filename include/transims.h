@@ -46,7 +46,7 @@
 extern "C" {
 #endif
 
-#define SIM_ABI_VERSION 2
+#define SIM_ABI_VERSION 3
 
 typedef enum {
   SIM_OK = 0,
@@ -120,6 +120,18 @@ typedef struct {
   const double* node_xy;   /* optional [2*n_nodes]; used only for tiling     */
   const float* link_cost;  /* optional [n_links] tiling weights (e.g. costs
                               measured by sim_link_costs on an earlier run)  */
+  /* optional fixed-time signals at the downstream end of links (Section
+     "Microsimulation driving logic": while the light is red a virtual
+     vehicle of speed zero stands at the end of the lane).  signal_plan[l]
+     is -1 or a plan index j < n_plans (1..63); plan j is red at step t iff
+     (t + plan_offset[j]) mod plan_cycle[j] < plan_red[j], cycle >= 1,
+     0 <= red <= cycle, offset >= 0.  While red, a lane's lead vehicle
+     neither crosses the node nor ends its trip there.  NULL = none.        */
+  const int8_t* signal_plan;
+  int32_t n_plans;
+  const int32_t* plan_cycle;
+  const int32_t* plan_red;
+  const int32_t* plan_offset;
 } sim_network;
 
 /* Travellers and their plans, borrowed for the duration of the call.

@@ -42,7 +42,9 @@ class _Network(C.Structure):
                 ("len", C.c_void_p), ("lanes", C.c_void_p),
                 ("rank", C.c_void_p), ("conn_off", C.c_void_p),
                 ("conn_out", C.c_void_p), ("conn_lo", C.c_void_p),
-                ("conn_hi", C.c_void_p)]
+                ("conn_hi", C.c_void_p), ("signal_plan", C.c_void_p),
+                ("n_plans", C.c_int32), ("plan_cycle", C.c_void_p),
+                ("plan_red", C.c_void_p), ("plan_offset", C.c_void_p)]
 
 
 class _Vehicles(C.Structure):
@@ -119,7 +121,11 @@ class OracleSim:
                        k(scen.link_to, np.int32), k(scen.link_len, np.int32),
                        k(scen.link_lanes, np.int8), k(scen.link_rank, np.int8),
                        k(scen.conn_off, np.int64), k(scen.conn_out, np.int32),
-                       k(scen.conn_lo, np.int8), k(scen.conn_hi, np.int8))
+                       k(scen.conn_lo, np.int8), k(scen.conn_hi, np.int8),
+                       k(scen.signal_plan, np.int8),
+                       0 if scen.plan_cycle is None else len(scen.plan_cycle),
+                       k(scen.plan_cycle, np.int32), k(scen.plan_red, np.int32),
+                       k(scen.plan_offset, np.int32))
         veh = _Vehicles(scen.n_veh, k(scen.depart, np.int32),
                         k(scen.route_off, np.int64),
                         k(scen.route_links, np.int32),

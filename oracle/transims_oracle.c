@@ -58,6 +58,16 @@
  *  R8  A vehicle that passes the link end lands at cell x+v3-len of lane k'
  *      of the next link; exit_t[route entry of the link it left] = t.  On
  *      the last link it is removed (ARRIVED, "exit to parking").
+ *
+ * Signalised turns (same section: a virtual vehicle of maximum speed zero
+ * stands at the end of the lane while the light is red):
+ *  S1  A link may carry a fixed-time plan (cycle C, red R, offset O); it is
+ *      red at step t iff (t + O) mod C < R, for all its lanes at once.
+ *  S2  The virtual vehicle stands just beyond the last cell: while red, the
+ *      lead vehicle of a lane of that link is no candidate at the node (no
+ *      claim, no trip end) and sees extra = 0, so it stops by the last cell.
+ *  S3  While green nothing changes: the unsignalised priority rule of R7
+ *      applies among the green approaches of the node.
  */
 #include "transims_oracle.h"
 
@@ -141,6 +151,8 @@ struct orc_sim {
   int64_t* conn_off;
   int32_t* conn_out;
   int8_t *conn_lo, *conn_hi;
+  int8_t* sig;       /* signal plan of the link, -1 = none                 */
+  int32_t *sig_cycle, *sig_red, *sig_off;
   int64_t* cell_off; /* lattice offset of (link, lane 0, cell 0)          */
   int64_t* lane_id;  /* global lane index of (link, lane 0)               */
   int64_t n_cells, n_lanes;
@@ -193,7 +205,8 @@ void orc_destroy(orc_sim* s) {
                   s->route_links, s->exit_t, s->status, s->lane,  s->x,
                   s->v,       s->rptr,     s->q_off,   s->q_ids,  s->q_head,
                   s->dec,     s->extra,    s->nx,      s->nv,     s->nlane,
-                  s->nlink,   s->lead_x,   s->lead_id, s->rear_x, s->best};
+                  s->nlink,   s->lead_x,   s->lead_id, s->rear_x, s->best,
+                  s->sig,     s->sig_cycle, s->sig_red, s->sig_off};
   for (size_t i = 0; i < sizeof(ptrs) / sizeof(ptrs[0]); ++i) free(ptrs[i]);
   free(s);
 }
@@ -276,6 +289,25 @@ orc_sim* orc_create(const orc_params* p, const orc_network* net,
     s->conn_out = (int32_t*)xcopy(net->conn_out, sizeof(int32_t) * nc);
     s->conn_lo = (int8_t*)xcopy(net->conn_lo, nc);
     s->conn_hi = (int8_t*)xcopy(net->conn_hi, nc);
+  }
+  /* signals (readings S1-S3) */
+  s->sig = (int8_t*)xcopy(NULL, L);
+  memset(s->sig, -1, L);
+  if (net->signal_plan && !s->ring) {
+    int32_t np = net->n_plans;
+    if (np < 1 || np > 63) FAIL("1..63 signal plans");
+    s->sig_cycle = (int32_t*)xcopy(net->plan_cycle, sizeof(int32_t) * np);
+    s->sig_red = (int32_t*)xcopy(net->plan_red, sizeof(int32_t) * np);
+    s->sig_off = (int32_t*)xcopy(net->plan_offset, sizeof(int32_t) * np);
+    for (int32_t j = 0; j < np; ++j)
+      if (s->sig_cycle[j] < 1 || s->sig_red[j] < 0 ||
+          s->sig_red[j] > s->sig_cycle[j] || s->sig_off[j] < 0)
+        FAIL("signal plan %d out of range", j);
+    for (int32_t l = 0; l < L; ++l) {
+      if (net->signal_plan[l] < -1 || net->signal_plan[l] >= np)
+        FAIL("link %d: signal plan out of range", l);
+      s->sig[l] = net->signal_plan[l];
+    }
   }
   s->occ = (int32_t*)malloc(sizeof(int32_t) * (s->n_cells ? s->n_cells : 1));
   for (int64_t c = 0; c < s->n_cells; ++c) s->occ[c] = -1;
@@ -496,7 +528,14 @@ static void account_lanes(orc_sim* s) {
     }
 }
 
-/* Reading R7. */
+/* Reading S1: is the light at the end of link l red in step t? */
+static int is_red(const orc_sim* s, int32_t l, int32_t t) {
+  int8_t j = s->sig[l];
+  if (j < 0) return 0;
+  return (int32_t)(((int64_t)t + s->sig_off[j]) % s->sig_cycle[j]) < s->sig_red[j];
+}
+
+/* Readings R7, S2, S3. */
 static void arbitrate(orc_sim* s) {
   int32_t vmax = s->p.vmax;
   for (int32_t i = 0; i < s->n; ++i) s->extra[i] = 0;
@@ -506,6 +545,7 @@ static void arbitrate(orc_sim* s) {
       for (int32_t k = 0; k < s->lanes[l]; ++k) {
         int32_t i = s->lead_id[s->lane_id[l] + k];
         if (i < 0 || s->len[l] - 1 - s->x[i] >= vmax) continue;
+        if (is_red(s, l, s->t)) continue; /* S2: the virtual vehicle */
         if (is_last_link(s, i)) {
           s->extra[i] = vmax;
           continue;

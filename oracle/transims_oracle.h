@@ -54,6 +54,14 @@ typedef struct {
   const int32_t* conn_out;
   const int8_t* conn_lo;
   const int8_t* conn_hi;
+  /* fixed-time signals at the downstream end of links (reading S1-S3):
+     signal_plan[l] = -1 (none) or a plan index; plan j is red at step t iff
+     (t + plan_offset[j]) mod plan_cycle[j] < plan_red[j].  NULL = none.    */
+  const int8_t* signal_plan; /* [n_links] or NULL */
+  int32_t n_plans;
+  const int32_t* plan_cycle; /* [n_plans], >= 1               */
+  const int32_t* plan_red;   /* [n_plans], 0..cycle           */
+  const int32_t* plan_offset;/* [n_plans], >= 0               */
 } orc_network;
 
 typedef struct {

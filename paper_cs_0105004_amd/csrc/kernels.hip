@@ -59,6 +59,23 @@ __device__ __forceinline__ int rec_slot(int base, int hc, int len, int j) {
   return base + hc_par(hc) * len + wrapi(hc_head(hc) + j, len);
 }
 
+// Is the fixed-time signal at the end of the lane's link red in step t?
+// (a virtual vehicle of speed zero then stands beyond the last cell)
+__device__ __forceinline__ bool sig_red(const int4* s_plans, uint32_t meta,
+                                        int t) {
+  const int pl = lmeta_plan(meta);
+  if (pl < 0) return false;
+  const int4 q = s_plans[pl];
+  return (int)(((uint32_t)t + (uint32_t)q.z) % (uint32_t)q.x) < q.y;
+}
+
+// The scenario's signal plans into LDS (thread j takes plan j); the caller
+// orders the writes before their first use.
+__device__ __forceinline__ void load_plans(const DevScen& S, int4* s_plans) {
+  const int i = threadIdx.x;
+  if (i < S.n_plans) s_plans[i] = S.plans[i];
+}
+
 __device__ __forceinline__ unsigned long long wave_sum(unsigned long long v) {
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
@@ -232,6 +249,7 @@ __global__ __launch_bounds__(kWave) void k_front(
   extern __shared__ unsigned char dyn[];
   __shared__ int4 s_info[kMaxTileLanes];
   __shared__ int s_hp[kMaxTileLanes], s_cnt[kMaxTileLanes];
+  __shared__ int4 s_plans[kMaxPlans];
   const long long c0 = wall_clock64();
   const int4 w = work[blockIdx.x];
   const DevScen& S = descs[kBatched ? w.x : slot];
@@ -265,6 +283,7 @@ __global__ __launch_bounds__(kWave) void k_front(
     qhead = lane_qhead[gid];
     qrec = lane_qrec[gid];
   }
+  load_plans(S, s_plans);
   const uint32_t meta = (uint32_t)info.y;
   const int len = act ? lmeta_len(meta) : 1;
   const int k = lmeta_k(meta), lanes = lmeta_lanes(meta);
@@ -346,10 +365,13 @@ __global__ __launch_bounds__(kWave) void k_front(
       }
     }
   }
+  __syncthreads();  // the plans in LDS (and the lane-change pass's writes)
   if (act) {
     int tgt = -1;
     const int rear_x = cnt > 0 ? xvf_x(rear_w) : len;
-    if (cnt > 0 && len - 1 - xvf_x(lead_w) < vmax) {
+    // a red light holds the lead vehicle back: no claim, no trip end
+    if (cnt > 0 && len - 1 - xvf_x(lead_w) < vmax &&
+        !sig_red(s_plans, meta, t)) {
       if (xvf_fl(lead_w) & kFlLast) {
         tgt = -2;  // the trip ends at this node
       } else {
@@ -797,6 +819,7 @@ __global__ __launch_bounds__(kWave) void k_step(
   __shared__ int2 s_second[kMaxTileLanes];  // the vehicle behind the lead
   __shared__ uint2 s_nhot[kMaxTileLanes][2];  // arrivals of this step
   __shared__ int2 s_ncold[kMaxTileLanes][2];
+  __shared__ int4 s_plans[kMaxPlans];
   const long long c0 = wall_clock64();
   const int4 w = work[blockIdx.x];
   const DevScen& S = descs[kBatched ? w.x : slot];
@@ -846,6 +869,7 @@ __global__ __launch_bounds__(kWave) void k_step(
     htag = ht_in[g];
     qn = qn_cur[g];
   }
+  load_plans(S, s_plans);
   const uint32_t meta = (uint32_t)bm.y;
   const int len = act ? lmeta_len(meta) : 1;
   const int k = lmeta_k(meta), lanes = lmeta_lanes(meta);
@@ -893,7 +917,10 @@ __global__ __launch_bounds__(kWave) void k_step(
   // 2. the lead vehicle at the node: target lane, its claim, and the
   // arrivals of the target link's lanes (read by every candidate, used by
   // the winner)
-  const bool cand = act && cnt > 0 && len - 1 - xvf_x(lead_w) < vmax;
+  // (a red light holds it back: no claim, no trip end)
+  wave_lds_sync();  // the plans in LDS
+  const bool cand = act && cnt > 0 && len - 1 - xvf_x(lead_w) < vmax &&
+                    !sig_red(s_plans, meta, t);
   const bool exits_here = cand && (xvf_fl(lead_w) & kFlLast);
   int tgt = exits_here ? -2 : -1, tm = 0, tlanes = 1, tl0 = 0;
   int claim = INT32_MAX, tqn = INT32_MAX;
@@ -1014,7 +1041,7 @@ __global__ __launch_bounds__(kWave) void k_step(
     }
     ls_nxt[g] = (v4i){e.x, e.y, e.z, hc_make(h1, 0, c1)};
     if (c1 > 0 && len - 1 - xvf_x((uint32_t)e.x) < vmax &&
-        !(xvf_fl((uint32_t)e.x) & kFlLast)) {
+        !(xvf_fl((uint32_t)e.x) & kFlLast) && !sig_red(s_plans, meta, t + 1)) {
       const uint32_t ni = (uint32_t)e.y;
       atomicMin((int*)&cl_nxt[rinfo_lane0(ni) + min(k, rinfo_lanes(ni) - 1)],
                 key);

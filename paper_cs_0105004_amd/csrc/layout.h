@@ -70,12 +70,17 @@ __host__ __device__ inline int hc_cnt(int h) { return (int)((uint32_t)h >> 16); 
 constexpr int kDepartBits = 27;
 
 // static per-lane word: len (bits 0-14), lane index k (15-16), lanes-1
-// (17-18), rank of the link at its downstream node (19-25)
+// (17-18), rank of the link at its downstream node (19-25), signal plan + 1
+// of the link (26-31, 0 = unsignalised)
 __host__ __device__ inline uint32_t lmeta_make(int len, int k, int lanes,
-                                               int rank) {
+                                               int rank, int plan = -1) {
   return (uint32_t)len | ((uint32_t)k << 15) | ((uint32_t)(lanes - 1) << 17) |
-         ((uint32_t)rank << 19);
+         ((uint32_t)rank << 19) | ((uint32_t)(plan + 1) << 26);
 }
+__host__ __device__ inline int lmeta_plan(uint32_t m) {
+  return (int)(m >> 26) - 1;
+}
+constexpr int kMaxPlans = 63;
 __host__ __device__ inline int lmeta_len(uint32_t m) { return (int)(m & 0x7FFFu); }
 __host__ __device__ inline int lmeta_k(uint32_t m) { return (int)((m >> 15) & 3u); }
 __host__ __device__ inline int lmeta_lanes(uint32_t m) {
@@ -130,6 +135,10 @@ struct DevScen {
   int32_t lc_desp;
   int32_t t;  // index of the next step
   int32_t n_links, n_lanes, n_tiles, n_ftiles, n_veh;
+  // fixed-time signal plans {cycle, red, offset, 0}: red at step t iff
+  // (t + offset) % cycle < red
+  int32_t n_plans;
+  const int4* plans;
   int32_t ring_L, ring_n;
   int32_t lc_cells;  // largest lanes*len of a link that changes lanes
   int64_t n_route;

@@ -149,6 +149,7 @@ void carve_network(Carve& cv, const NetDims& nd, DevScen& d, bool ring) {
   d.hand_b = cv.take<int32_t>(2 * Q);
   d.qnext = cv.take<int32_t>(2 * Q);
   d.lane_bm = cv.take<int2>(Q);
+  d.plans = cv.take<int4>(kMaxPlans);
   d.lane_qend = cv.take<int32_t>(Q);
   d.hand_tag = cv.take<int32_t>(2 * Q);
   d.lane_qhead = cv.take<int32_t>(Q);
@@ -220,6 +221,19 @@ sim_status check_network(sim_ctx* c, const sim_params* p, const sim_network* n) 
       return fail(c, SIM_E_CAPACITY,
                   "link %d: lane changing supports links up to %d cells", l,
                   kLcMaxLen);
+  }
+  if (n->signal_plan) {
+    if (n->n_plans < 1 || n->n_plans > kMaxPlans)
+      return fail(c, SIM_E_INVAL, "1..%d signal plans", kMaxPlans);
+    if (!n->plan_cycle || !n->plan_red || !n->plan_offset)
+      return fail(c, SIM_E_INVAL, "signal plan arrays are NULL");
+    for (int32_t j = 0; j < n->n_plans; ++j)
+      if (n->plan_cycle[j] < 1 || n->plan_red[j] < 0 ||
+          n->plan_red[j] > n->plan_cycle[j] || n->plan_offset[j] < 0)
+        return fail(c, SIM_E_INVAL, "signal plan %d out of range", j);
+    for (int32_t l = 0; l < n->n_links; ++l)
+      if (n->signal_plan[l] < -1 || n->signal_plan[l] >= n->n_plans)
+        return fail(c, SIM_E_INVAL, "link %d: signal plan out of range", l);
   }
   if (p->flags & SIM_FLAG_TURN_LANES) {
     if (!n->conn_off || !n->conn_out || !n->conn_lo || !n->conn_hi)
@@ -441,7 +455,11 @@ extern "C" sim_status sim_load_network(sim_ctx* c, int32_t slot,
     const int rank = S.ring ? 0 : net->rank[order[i]];
     for (int k = 0; k < S.lanes[i]; ++k) {
       lane_info[S.lane0[i] + k] =
-          make_int4((int32_t)rec, (int32_t)lmeta_make(S.len[i], k, S.lanes[i], rank), i, 0);
+          make_int4((int32_t)rec,
+                    (int32_t)lmeta_make(S.len[i], k, S.lanes[i], rank,
+                                        (!S.ring && net->signal_plan)
+                                            ? net->signal_plan[order[i]] : -1),
+                    i, 0);
       rec += cap;
     }
     if (rec > INT32_MAX) return fail(c, SIM_E_CAPACITY, "too many cells");
@@ -470,12 +488,20 @@ extern "C" sim_status sim_load_network(sim_ctx* c, int32_t slot,
   d.n_tiles = S.n_tiles;
   d.n_ftiles = S.n_ftiles;
   d.xcap = (S.ring || S.fused) ? 0 : (int32_t)extra_cap(S.n_ftiles, c->cfg.back_pieces);
+  d.n_plans = (!S.ring && net->signal_plan) ? net->n_plans : 0;
   d.fused = S.fused ? 1 : 0;
   d.lc_cells = S.lc_cells;
   d.ring_L = S.ring ? net->len[0] : 0;
   hipStream_t s = c->stream;
   HIPCHK(c, up(const_cast<int32_t*>(d.link_ext), S.ext_of.data(), L, s));
   HIPCHK(c, up(const_cast<int4*>(d.lane_info), lane_info.data(), S.n_lanes, s));
+  if (d.n_plans > 0) {
+    std::vector<int4> plans(d.n_plans);
+    for (int32_t j = 0; j < d.n_plans; ++j)
+      plans[j] = make_int4(net->plan_cycle[j], net->plan_red[j],
+                           net->plan_offset[j] % net->plan_cycle[j], 0);
+    HIPCHK(c, up(const_cast<int4*>(d.plans), plans.data(), d.n_plans, s));
+  }
   {
     std::vector<int2> bm(S.n_lanes);
     for (int32_t qq = 0; qq < S.n_lanes; ++qq)

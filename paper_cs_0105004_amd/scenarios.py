@@ -61,6 +61,13 @@ class Scenario:
     conn_lo: Optional[np.ndarray] = None   # int8
     conn_hi: Optional[np.ndarray] = None   # int8
     node_xy: Optional[np.ndarray] = None   # float64 [n_nodes, 2]
+    # fixed-time signals at the downstream end of links: plan index per link
+    # (-1: none); plan j is red at step t iff (t + offset[j]) % cycle[j] <
+    # red[j]
+    signal_plan: Optional[np.ndarray] = None  # int8 [n_links]
+    plan_cycle: Optional[np.ndarray] = None   # int32 [n_plans]
+    plan_red: Optional[np.ndarray] = None     # int32
+    plan_offset: Optional[np.ndarray] = None  # int32
     # vehicles
     n_veh: int = 0
     depart: np.ndarray = None      # int32
@@ -352,11 +359,16 @@ def grid_scenario(rows: int, cols: int, n_links: int, n_veh: int, T: int,
                   depart_max: int, seed: int, vmax: int = 5, p="0.2",
                   lanes_range=(1, 3), flags: int = 0, len_sampler=None,
                   depart_sampler=None, sim_seed: Optional[int] = None,
-                  n_origins: int = 0, name: str = "grid") -> Scenario:
+                  n_origins: int = 0, signals: Optional[tuple] = None,
+                  name: str = "grid") -> Scenario:
     """Grid network with n_veh vehicles routed by shortest path between
     distinct uniformly random nodes, departing uniformly in [0, depart_max].
     n_origins > 0 draws the origins from that many random nodes only (trip
-    generation zones), which bounds the routing work of large demands."""
+    generation zones), which bounds the routing work of large demands.
+    signals = (cycle, red) puts fixed-time signals on every node that at
+    least three links enter: its east-west approaches are red in the first
+    `red` steps of each cycle, its north-south approaches `cycle // 2` steps
+    later (the paper's validation signal is 30 s red, 30 s green)."""
     rng = np.random.Generator(np.random.PCG64(seed))
     frm, to, length, lanes, xy = grid_network(rows, cols, n_links, rng,
                                               lanes_range, len_sampler)
@@ -377,6 +389,18 @@ def grid_scenario(rows: int, cols: int, n_links: int, n_veh: int, T: int,
         depart = rng.integers(0, depart_max + 1, size=n_veh).astype(np.int32)
     else:
         depart = depart_sampler(rng, n_veh).astype(np.int32)
+    sig = {}
+    if signals is not None:
+        cycle, red = int(signals[0]), int(signals[1])
+        indeg = np.bincount(to, minlength=n_nodes)
+        d = xy[to] - xy[frm]
+        ew = np.abs(d[:, 0]) >= np.abs(d[:, 1])
+        plan = np.where(ew, 0, 1).astype(np.int8)
+        plan[indeg[to] < 3] = -1
+        sig = dict(signal_plan=plan,
+                   plan_cycle=np.array([cycle, cycle], np.int32),
+                   plan_red=np.array([red, red], np.int32),
+                   plan_offset=np.array([0, cycle // 2], np.int32))
     return Scenario(
         name=name, flags=flags, vmax=vmax, slow_thr=prob_threshold(p),
         seed=int(seed if sim_seed is None else sim_seed), T=T,
@@ -384,7 +408,7 @@ def grid_scenario(rows: int, cols: int, n_links: int, n_veh: int, T: int,
         link_lanes=lanes, link_rank=rank, conn_off=conn_off,
         conn_out=conn_out, conn_lo=conn_lo, conn_hi=conn_hi, node_xy=xy,
         n_veh=n_veh, depart=depart, route_off=route_off,
-        route_links=route_links)
+        route_links=route_links, **sig)
 
 
 def loop_of_links(lengths, n: int, vmax: int = 5, p="0.2", seed: int = 1,
@@ -463,7 +487,8 @@ def chain(lengths, lanes=None, depart=(0,), vmax: int = 5, p="0", seed=3,
 
 
 def portland_like(seed: int = 2024, scale: float = 1.0, T: int = 3600,
-                  flags: int = 0, depart_max: int = 1799) -> Scenario:
+                  flags: int = 0, depart_max: int = 1799,
+                  signals: Optional[tuple] = None) -> Scenario:
     """Portland-sized grid: 77 x 78 = 6,006 nodes thinned to 20,024 directed
     links of 1-3 lanes, edge lengths uniform in 20..200 cells, 200,000
     vehicles with shortest-path routes between random distinct nodes,
@@ -480,7 +505,8 @@ def portland_like(seed: int = 2024, scale: float = 1.0, T: int = 3600,
         links = 2 * und
         nveh = max(1, int(round(200000 * scale)))
     return grid_scenario(rows, cols, links, nveh, T, depart_max, seed,
-                         flags=flags, name=f"portland_like(scale={scale})")
+                         flags=flags, signals=signals,
+                         name=f"portland_like(scale={scale})")
 
 
 def _grid_shape(n_links: int):

@@ -17,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libtransims.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "transims.h")
 
-ABI_VERSION = 2
+ABI_VERSION = 3
 OK, E_INVAL, E_NOMEM, E_STATE, E_DEVICE, E_CAPACITY, E_ABI = 0, -1, -2, -3, -4, -5, -6
 STATUS_NAMES = {0: "SIM_OK", -1: "SIM_E_INVAL", -2: "SIM_E_NOMEM",
                 -3: "SIM_E_STATE", -4: "SIM_E_DEVICE", -5: "SIM_E_CAPACITY",
@@ -50,7 +50,10 @@ class sim_network(C.Structure):
                 ("lanes", C.c_void_p), ("rank", C.c_void_p),
                 ("conn_off", C.c_void_p), ("conn_out", C.c_void_p),
                 ("conn_lo", C.c_void_p), ("conn_hi", C.c_void_p),
-                ("node_xy", C.c_void_p), ("link_cost", C.c_void_p)]
+                ("node_xy", C.c_void_p), ("link_cost", C.c_void_p),
+                ("signal_plan", C.c_void_p), ("n_plans", C.c_int32),
+                ("plan_cycle", C.c_void_p), ("plan_red", C.c_void_p),
+                ("plan_offset", C.c_void_p)]
 
 
 class sim_vehicles(C.Structure):
@@ -162,7 +165,10 @@ class _Inputs:
             k(scen.conn_lo, np.int8), k(scen.conn_hi, np.int8),
             k(None if scen.node_xy is None else scen.node_xy.ravel(),
               np.float64),
-            k(link_cost, np.float32))
+            k(link_cost, np.float32), k(scen.signal_plan, np.int8),
+            0 if scen.plan_cycle is None else len(scen.plan_cycle),
+            k(scen.plan_cycle, np.int32), k(scen.plan_red, np.int32),
+            k(scen.plan_offset, np.int32))
         self.veh = sim_vehicles(
             scen.n_veh, k(scen.depart, np.int32), k(scen.route_off, np.int64),
             k(scen.route_links, np.int32), k(scen.init_status, np.int8),
