@@ -1,0 +1,62 @@
+"""Emergent flow characteristics (the paper's Figure 4 sweeps) measured on
+the GPU: the deterministic ring's closed form at every density, and the
+qualitative shape of the other diagrams; one merge scenario against the
+oracle."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_cs_0105004_amd import scenarios as S
+from paper_cs_0105004_amd import validation as V
+from parity import assert_same_state, assert_same_stats
+
+pytestmark = pytest.mark.gpu
+
+
+def test_ring_fundamental_diagram():
+    dens = [0.02, 0.06, 0.1, 0.14, 0.2, 0.3, 0.5, 0.7, 0.9]
+    rows = V.ring_diagram(L=500, densities=dens, ps=("0", "0.2"), warm=800,
+                          measure=400)
+    det = {r["density"]: r["flow"] for r in rows if r["p"] == 0.0}
+    sto = {r["density"]: r["flow"] for r in rows if r["p"] == 0.2}
+    for rho, f in det.items():  # p = 0: flow = min(rho vmax, 1 - rho)
+        assert f == pytest.approx(min(rho * 5, 1 - rho), abs=1e-12)
+    for rho in dens:
+        assert sto[rho] < det[rho]
+    peak = max(sto, key=sto.get)
+    assert peak <= 0.2 and sto[0.9] < sto[peak] / 3
+
+
+def test_three_lane_loop():
+    rows = V.multilane_diagram(densities=[0.05, 0.15, 0.7], warm=600,
+                               measure=600)
+    f = {round(r["density"], 2): r for r in rows}
+    assert f[0.15]["lane_changes_per_step"] > 0
+    assert f[0.7]["flow"] < f[0.15]["flow"]
+    assert all(r["flow"] > 0 for r in rows)
+
+
+def test_stop_sign_and_signal_shapes():
+    ss = V.stop_sign(main_rates=[0.0, 0.5, 1.4], T=1500, warm=300)
+    side = [r["side_flow"] for r in ss]
+    assert side[0] > side[1] > side[2]
+    sg = V.signal(demands=[0.1, 1.6, 2.0], T=1500, warm=300)
+    assert sg[0]["main_flow"] == pytest.approx(0.1, abs=0.04)  # all pass
+    # saturated: the red half of the cycle caps the flow
+    assert sg[2]["main_flow"] == pytest.approx(sg[1]["main_flow"], rel=0.1)
+    assert sg[2]["main_flow"] < 1.0
+
+
+def test_merge_scenario_matches_oracle():
+    from paper_cs_0105004_amd.sim import Context
+    scen, _ = V._merge_network(0.6, 0.5, 600, seed=9, signal=None)
+    sig, _ = V._merge_network(1.2, 0.0, 600, seed=10, signal=(60, 30))
+    for sc in (scen, sig):
+        ctx = Context(max_slots=1)
+        ctx.load(0, sc)
+        ctx.step(0, 600)
+        o = oracle.OracleSim(sc)
+        o.step(600)
+        assert_same_stats(ctx.stats(0), o.stats(), "merge")
+        assert_same_state(ctx.state(0), o.state(), "merge")
+        ctx.close()
