@@ -272,16 +272,19 @@ __global__ __launch_bounds__(kWave) void k_front(
   const int gid = w.y + i;
 
   // everything this kernel reads of a lane, in one round of loads
-  v4i info = {0, 0, 0, 0}, st = {0, 0, 0, 0}, ha = {0, 0, 0, 0};
-  v4i qrec = {-1, 0, 0, 0};
-  int hb = 0, qhead = 0;
-  if (act) {
-    info = lane_info[gid];
-    st = lane_state[gid];
-    ha = hand_a[gid];
-    hb = hand_b[gid];
-    qhead = lane_qhead[gid];
-    qrec = lane_qrec[gid];
+  // (threads past the tile's lanes read its first lane and drop it, so
+  // that no load waits behind a branch)
+  const int gg = act ? gid : w.y;
+  v4i info = lane_info[gg], st = lane_state[gg], ha = hand_a[gg];
+  v4i qrec = lane_qrec[gg];
+  int hb = hand_b[gg], qhead = lane_qhead[gg];
+  if (!act) {
+    info = (v4i){0, 0, 0, 0};
+    st = (v4i){0, 0, 0, 0};
+    ha = (v4i){0, 0, 0, 0};
+    qrec = (v4i){-1, 0, 0, 0};
+    hb = 0;
+    qhead = 0;
   }
   load_plans(S, s_plans);
   const uint32_t meta = (uint32_t)info.y;
@@ -860,14 +863,17 @@ __global__ __launch_bounds__(kWave) void k_step(
   // 1. what every lane needs from the previous step, in one round: its
   // static word, its state, the tag of the last handoff into it and (lane
   // 0) the departure time of its link's queue head
-  v2i bm = {0, 0};
-  v4i st = {0, 0, 0, 0};
-  int htag = kTagNone, qn = INT32_MAX;
-  if (act) {
-    bm = lane_bm[g];
-    st = ls_cur[g];
-    htag = ht_in[g];
-    qn = qn_cur[g];
+  // (threads past the tile's lanes read its first lane and drop it, so
+  // that no load waits behind a branch)
+  const int gg = act ? g : w.y;
+  v2i bm = lane_bm[gg];
+  v4i st = ls_cur[gg];
+  int htag = ht_in[gg], qn = qn_cur[gg];
+  if (!act) {
+    bm = (v2i){0, 0};
+    st = (v4i){0, 0, 0, 0};
+    htag = kTagNone;
+    qn = INT32_MAX;
   }
   load_plans(S, s_plans);
   const uint32_t meta = (uint32_t)bm.y;

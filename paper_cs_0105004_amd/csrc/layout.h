@@ -126,53 +126,60 @@ enum : int {
 // other one.  With `fused` == 0 only buffer 0 is used.
 
 struct DevScen {
-  uint32_t flags;
-  int32_t fused;  // 1: one kernel per step, parity-buffered state
-  int32_t vmax;
-  uint32_t key0, key1;  // Philox key = seed
-  uint64_t slow_thr;
-  uint64_t lc_thr;
-  int32_t lc_desp;
+  // ---- what every step kernel reads first, kept contiguous so that it
+  // arrives in one round of wide scalar loads ----
   int32_t t;  // index of the next step
-  int32_t n_links, n_lanes, n_tiles, n_ftiles, n_veh;
+  int32_t n_lanes;
+  int32_t vmax;
+  int32_t n_plans;
+  // lanes: lane_bm {record base, lmeta}; lane_state[2][n_lanes] {lead xvf,
+  // lead ninfo, rear xvf, hc} at the end of a step (one buffer without
+  // fused stepping); hand_tag (fused) t << 1 | (landed on cell 0) of the
+  // last handoff into the lane in a step of that parity; qnext (fused) the
+  // departure of the link's parking-queue head (INT32_MAX: empty), at lane 0
+  const int2* lane_bm;
+  int4* lane_state;
+  int32_t* hand_tag;
+  int32_t* qnext;
   // fixed-time signal plans {cycle, red, offset, 0}: red at step t iff
   // (t + offset) % cycle < red
-  int32_t n_plans;
   const int4* plans;
-  int32_t ring_L, ring_n;
-  int32_t lc_cells;  // largest lanes*len of a link that changes lanes
-  int64_t n_route;
-  // links, in the library's internal (tile) order
-  const int32_t* link_ext;    // caller's link id
-  // lanes: {record base, lmeta, link, end of the link's parking queue}
-  const int4* lane_info;
-  int4* lane_state;          // {lead xvf, lead ninfo, rear xvf, hc} after
-                             // the move sub-step
-  int4* lane_sum;            // {target, rear x, hc, 0} after sub-step 1
-  int32_t* claim;            // smallest (rank, lane) key aiming at the lane
-  int4* hand_a;              // arrival handoff {tag = t, xvf, id, rp}
-  int32_t* hand_b;           // arrival handoff: ninfo
+  // arrival handoff per target lane: hand_a {tag = t, xvf, id, rp}, hand_b
+  // ninfo
+  int4* hand_a;
+  int32_t* hand_b;
+  int32_t* claim;  // smallest (rank, lane) key aiming at the lane
   // parking queue of a link, kept with its lane 0: the index of its head in
-  // wait_rec and a copy of that record (id -1: to be fetched again)
+  // wait_rec and a copy of that record (id -1: to be fetched again), and
+  // its end
   int32_t* lane_qhead;
   int4* lane_qrec;
-  // fused: depart of the link's queue head (INT32_MAX: empty), at lane 0
-  int32_t* qnext;
-  // fused: what the one-kernel step reads of every lane, kept small --
-  //   lane_bm {record base, lmeta}; hand_tag[2][n_lanes] = t << 1 | (landed
-  //   on cell 0) of the last vehicle handed over to the lane in a step of
-  //   that parity (its record is in hand_a / hand_b); lane_qend at lane 0:
-  //   end of the link's parking queue in wait_rec
-  const int2* lane_bm;
-  int32_t* hand_tag;
   const int32_t* lane_qend;
+  const int4* wait_rec;  // parking queues, link by link, by (depart, id)
   // vehicle records
   uint2* hot;
   int2* cold;
-  // tiles: the front kernel works on small tiles (one wavefront), the back
-  // kernel on large ones (several wavefronts share the vehicles)
-  long long* tile_ctr;     // [n_lanes * C_N], move runs (by first lane)
-  long long* ftile_ctr;    // [n_ftiles * C_N], front tiles
+  // routes
+  const uint32_t* route_info;
+  int32_t* exit_t;
+  long long* tile_ctr;  // [n_lanes * C_N], counters by a tile's first lane
+  uint32_t* err;
+  uint32_t key0, key1;  // Philox key = seed
+  uint64_t slow_thr;
+  // ---- the rest ----
+  uint32_t flags;
+  int32_t fused;  // 1: one kernel per step, parity-buffered state
+  uint64_t lc_thr;
+  int32_t lc_desp;
+  int32_t n_links, n_tiles, n_ftiles, n_veh;
+  int32_t ring_L, ring_n;
+  int32_t lc_cells;  // largest lanes*len of a link that changes lanes
+  int64_t n_route;
+  const int32_t* link_ext;  // caller's link id, in the internal order
+  // lanes: {record base, lmeta, link, end of the link's parking queue}
+  const int4* lane_info;
+  int4* lane_sum;  // two-kernel step: {target, rear x, hc, 0} after sub-step 1
+  long long* ftile_ctr;  // [n_ftiles * C_N], front tiles
   // Heavy tiles get extra move wavefronts: the front kernel decides each
   // tile's number of runs (tile_np) and lists the runs beyond the first in
   // xlist {first lane, lanes | run << 8 | runs << 16, tile, 0}; xcount[t & 1]
@@ -181,18 +188,12 @@ struct DevScen {
   int4* xlist;
   int32_t* xcount;
   int32_t xcap;  // entries of xlist (0: every tile is one run)
-  // parking queues, link by link, each ordered by (depart, id)
-  const int4* wait_rec;
-  // routes
   const int64_t* route_off;
-  const uint32_t* route_info;
-  int32_t* exit_t;
   // ring mode (vehicles in cyclic order)
   int32_t* ring_x;
   int32_t* ring_v;
   const int32_t* ring_id;
   long long* ring_ctr;  // [C_N]
-  uint32_t* err;
 };
 
 }  // namespace tr

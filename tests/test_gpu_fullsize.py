@@ -51,3 +51,32 @@ def test_portland_configs_agree(portland, mode, lanes, cells, pieces, graph):
     assert_same_state(alt.state(0), ref.state(0), "configs")
     ref.close()
     alt.close()
+
+
+def test_batched_replications_full_size_sampled():
+    # all 64 replications (417k links, 4.1M vehicles) in the launch
+    # configuration the batched benchmark picks, full 3,600 steps; the three
+    # smallest are compared with the oracle vehicle by vehicle, every one
+    # against counters that hold at any size
+    import numpy as np
+    from paper_cs_0105004_amd.sim import Context
+    scens = S.batched_scenarios()
+    ctx = Context(max_slots=len(scens), tile_lanes=64, tile_cells=16384,
+                  graph_steps=64)
+    for k, sc in enumerate(scens):
+        ctx.load(k, sc)
+    ctx.step(list(range(len(scens))), 3600)
+    for k, sc in enumerate(scens):
+        st = ctx.stats(k)
+        assert st["dev_err"] == 0
+        assert st["n_waiting"] + st["n_active"] + st["n_arrived"] == sc.n_veh
+        assert st["insertions"] == sc.n_veh - st["n_waiting"]
+        assert st["exits"] == st["n_arrived"]
+    order = np.argsort([sc.n_veh for sc in scens])[:3]
+    for k in order:
+        o = oracle.OracleSim(scens[k])
+        o.step(3600)
+        print("replication", k, scens[k].n_links, "links", flush=True)
+        assert_same_stats(ctx.stats(k), o.stats(), f"replication {k}")
+        assert_same_state(ctx.state(k), o.state(), f"replication {k}")
+    ctx.close()
