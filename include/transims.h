@@ -84,9 +84,10 @@ typedef struct {
                            cells, two kernels (lane-change / move sub-step)
                            otherwise; 1 = always two kernels.  Results are
                            the same either way.                             */
-  int32_t tile_cells;   /* one-kernel step: a tile also stops at this many
-                           cells (len x lanes; a longer link is a tile of
-                           its own), 64..65536; 0 = default (2048)          */
+  int32_t tile_cells;   /* one-kernel step, and scenarios with lane
+                           changes: a tile also stops at this many cells
+                           (len x lanes; a longer link is a tile of its
+                           own), 64..65536; 0 = default (2048)              */
   int32_t reserved;     /* must be 0                                        */
 } sim_config;
 

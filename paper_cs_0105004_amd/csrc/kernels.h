@@ -12,10 +12,12 @@ namespace tr {
 // the front kernel merges arrivals, lets vehicles leave parking, runs the
 // lane-change sub-step and publishes per-lane summaries; the back kernel
 // resolves the intersections and moves every vehicle (second sub-step).
-// lc_cells: largest lanes*len over links that change lanes (LDS lattice).
+// lc_words: most lattice words of a tile's lane-changing links (each lane
+// ceil(len/32) words); the lane-change sub-step takes kLcBytesPerWord bytes
+// of LDS per word.
 // pieces: most move wavefronts per tile (single slot; 1 = one per tile)
 hipError_t launch_front(const DevScen* d_descs, int slot, const int4* d_work,
-                        int n_work, int pieces, int step, int lc_cells,
+                        int n_work, int pieces, int step, int lc_words,
                         hipStream_t s);
 // The move kernel: one wavefront per work item plus, for a single slot,
 // n_extra wavefronts for the runs of heavy tiles the front kernel listed.
@@ -34,6 +36,11 @@ void* front_kernel(bool batched);
 void* back_kernel(bool batched);
 void* advance_kernel();
 constexpr int kFrontThreads = kWave, kBackThreadsPerPiece = kWave;
+constexpr int kLcBytesPerWord = 14;
+// A link has at most 4 lanes of at most 32767 cells (1024 words each), and a
+// tile of lane-changing links with more than one link holds at most
+// tile_cells <= 65536 cells, so no tile needs more words than this.
+constexpr int kMaxLcWords = 4096;
 // descs[slots[i]].t += k for i < n
 hipError_t launch_advance(DevScen* d_descs, const int* d_slots, int n, int k,
                           hipStream_t s);

@@ -83,52 +83,77 @@ __device__ __forceinline__ unsigned long long wave_sum(unsigned long long v) {
 }
 
 // ---- lane change on one tile ------------------------------------------
-// Empty cells of lane m ahead of x up to the first vehicle or the link end,
+// The lane-change sub-step of a tile works on bit lattices in LDS, one bit
+// per cell.  Each lane of a link that changes lanes is padded to whole
+// 32-bit words, so word q of lane k and word q of lane k +- 1 (q +- wpl)
+// cover the same cells.  Per word of the tile (kLcBytesPerWord bytes):
+//   occ  occupied cells before the sub-step; after the decisions, after it
+//   rgt  vehicles moving one lane up (k -> k+1)
+//   lft  vehicles moving one lane down (k -> k-1)
+//   pre  running count of the new occupancy over the tile's words, mod 2^16
+//        (a lane holds at most 32767 vehicles, so differences within one
+//        lane are exact)
+struct LcLat {
+  uint32_t* occ;
+  uint32_t* rgt;
+  uint32_t* lft;
+  uint16_t* pre;
+};
+
+// cells [c, c+32) of a lane of wpl words at w, cell c at bit 0; cells
+// outside the lane read as empty (c may be negative)
+__device__ __forceinline__ uint32_t lane_bits(const uint32_t* w, int wpl,
+                                              int c) {
+  const int q = c >> 5, sh = c & 31;
+  const uint32_t lo = (q >= 0 && q < wpl) ? w[q] : 0u;
+  const uint32_t hi = (q + 1 >= 0 && q + 1 < wpl) ? w[q + 1] : 0u;
+  return sh == 0 ? lo : (lo >> sh) | (hi << (32 - sh));
+}
+
+__device__ __forceinline__ bool lane_bit(const uint32_t* w, int x) {
+  return (w[x >> 5] >> (x & 31)) & 1u;
+}
+
+// Empty cells of a lane ahead of x up to the first vehicle or the link end,
 // and behind x up to the first vehicle (cells before the link start count as
-// empty), both capped at vmax.
-__device__ __forceinline__ int lc_ahead(const short* lat, int len, int m,
+// empty), both capped at vmax (at most 7).
+__device__ __forceinline__ int lc_ahead(const uint32_t* w, int wpl, int len,
                                         int x, int vmax) {
-  int n = 0;
-  for (int c = x + 1; c < len && n < vmax; ++c) {
-    if (lat[m * len + c] >= 0) break;
-    ++n;
-  }
-  return n;
+  const int lim = min(vmax, len - 1 - x);
+  return (int)__builtin_ctz(lane_bits(w, wpl, x + 1) | (1u << lim));
 }
 
-__device__ __forceinline__ int lc_behind(const short* lat, int len, int m,
-                                         int x, int vmax) {
-  int n = 0;
-  for (int c = x - 1; n < vmax; --c) {
-    if (c >= 0 && lat[m * len + c] >= 0) break;
-    ++n;
-  }
-  return n;
+__device__ __forceinline__ int lc_behind(const uint32_t* w, int wpl, int x,
+                                         int vmax) {
+  const uint32_t b = lane_bits(w, wpl, x - vmax) & ((1u << vmax) - 1u);
+  return b == 0u ? vmax : vmax - 1 - (31 - (int)__builtin_clz(b));
 }
 
-__device__ int lc_decide(const DevScen& S, const short* lat, int len,
-                         int lanes, int k, int x, int v, uint32_t fl, int id,
-                         int t) {
+// Target lane of the vehicle at cell x of lane k, or -1; wk: lane k's words
+__device__ int lc_decide(const DevScen& S, const uint32_t* wk, int wpl,
+                         int len, int lanes, int k, int x, int v, uint32_t fl,
+                         int id, int t) {
   const int vmax = S.vmax;
   const int lo = fl_lo(fl), hi = fl_hi(fl);
   if (k < lo || k > hi) {  // mandatory: one lane toward the turn lanes
     const int m = k < lo ? k + 1 : k - 1;
+    const uint32_t* wm = wk + (m - k) * wpl;
     const int need = min(vmax, (len - 1 - x) / S.lc_desp);
-    if (lat[m * len + x] < 0 && lc_behind(lat, len, m, x, vmax) >= need)
-      return m;
+    if (!lane_bit(wm, x) && lc_behind(wm, wpl, x, vmax) >= need) return m;
     return -1;
   }
-  const int own = lc_ahead(lat, len, k, x, vmax);
+  const int own = lc_ahead(wk, wpl, len, x, vmax);
   if (own >= min(v + 1, vmax)) return -1;
   int best = -1, best_a = -1;
 #pragma unroll
   for (int s = 0; s < 2; ++s) {
     const int m = s == 0 ? k - 1 : k + 1;
     if (m < 0 || m >= lanes || m < lo || m > hi) continue;
-    if (lat[m * len + x] >= 0) continue;
-    const int a = lc_ahead(lat, len, m, x, vmax);
+    const uint32_t* wm = wk + (m - k) * wpl;
+    if (lane_bit(wm, x)) continue;
+    const int a = lc_ahead(wm, wpl, len, x, vmax);
     if (a <= own) continue;
-    if (lc_behind(lat, len, m, x, vmax) < vmax) continue;
+    if (lc_behind(wm, wpl, x, vmax) < vmax) continue;
     if (a > best_a) {
       best = m;
       best_a = a;
@@ -141,98 +166,214 @@ __device__ int lc_decide(const DevScen& S, const short* lat, int len,
   return best;
 }
 
-// Runs the lane-change sub-step on every multi-lane link of the tile.  The
-// link's lanes are staged in LDS as a lattice of record offsets; movers are
-// applied at once and, when any vehicle moved, the lanes' queues are
-// rebuilt in the other half of their double buffer.  s_info/s_hp/s_cnt hold
-// the tile's lanes.
-__device__ int lane_change_tile(const DevScen& S, int t, int nl,
-                                const int4* s_info, int* s_hp, int* s_cnt,
-                                short* lat, signed char* dec) {
+__device__ __forceinline__ int wave_incl_scan(int v) {
   const int i = threadIdx.x;
-  int moves_total = 0;
-  for (int tb = 0; tb < nl; ++tb) {
-    const uint32_t meta = (uint32_t)s_info[tb].y;
-    const int lanes = lmeta_lanes(meta);
-    if (lmeta_k(meta) != 0 || lanes < 2) continue;
-    int pre[5];
-    pre[0] = 0;
-    for (int k = 0; k < lanes; ++k) pre[k + 1] = pre[k] + s_cnt[tb + k];
-    const int total = pre[lanes];
-    if (total == 0) continue;
-    const int len = lmeta_len(meta);
-    const int region = s_info[tb].x;  // lanes' double buffers are contiguous
-    const int cells = lanes * len;
-    for (int c = i; c < cells; c += kWave) {
-      lat[c] = -1;
-      dec[c] = -1;
-    }
-    __syncthreads();
-    for (int f = i; f < total; f += kWave) {
-      int k = 0;
-      while (f >= pre[k + 1]) ++k;
-      const int slot = rec_slot(s_info[tb + k].x, s_hp[tb + k], len, f - pre[k]);
-      lat[k * len + xvf_x(S.hot[slot].x)] = (short)(slot - region);
-    }
-    __syncthreads();
-    for (int f = i; f < total; f += kWave) {
-      int k = 0;
-      while (f >= pre[k + 1]) ++k;
-      const int slot = rec_slot(s_info[tb + k].x, s_hp[tb + k], len, f - pre[k]);
-      const uint2 hw = S.hot[slot];
-      const int x = xvf_x(hw.x);
-      const int d = lc_decide(S, lat, len, lanes, k, x, xvf_v(hw.x),
-                              xvf_fl(hw.x), (int)hw.y, t);
-      if (d >= 0) dec[k * len + x] = (signed char)d;
-    }
-    __syncthreads();
-    // two movers into one cell come from both sides of it: the one from the
-    // lower lane moves, the one moving left stays
-    for (int c = i; c < cells; c += kWave) {
-      const int d = dec[c];
-      if (d < 0) continue;
-      const int k = c / len, x = c - (c / len) * len;
-      if (d == k - 1 && d - 1 >= 0 && dec[(d - 1) * len + x] == d)
-        dec[c] = -2;
-    }
-    __syncthreads();
-    int moved = 0;
-    for (int c = i; c < cells; c += kWave) {
-      const int d = dec[c];
-      if (d < 0) continue;
-      const int x = c - (c / len) * len;
-      lat[d * len + x] = lat[c];
-      lat[c] = -1;
-      ++moved;
-    }
-    moved = (int)wave_sum((unsigned long long)moved);
-    __syncthreads();
-    if (moved > 0) {
-      const int npar = 1 - hc_par(s_hp[tb]);
-      for (int k = 0; k < lanes; ++k) {
-        const int dst0 = s_info[tb + k].x + npar * len;
-        int n = 0;
-        for (int c0 = 0; c0 < len; c0 += kWave) {
-          const int x = len - 1 - (c0 + i);
-          const short o = x >= 0 ? lat[k * len + x] : (short)-1;
-          const unsigned long long m = __ballot(o >= 0);
-          if (o >= 0) {
-            const int j = n + __popcll(m & ((1ull << i) - 1ull));
-            S.hot[dst0 + j] = S.hot[region + o];
-            S.cold[dst0 + j] = S.cold[region + o];
-          }
-          n += __popcll(m);
-        }
-        if (i == 0) {
-          s_hp[tb + k] = hc_make(0, npar, 0);
-          s_cnt[tb + k] = n;
-        }
-      }
-      __syncthreads();
-      moves_total += moved;
+#pragma unroll
+  for (int off = 1; off < kWave; off <<= 1) {
+    const int u = __shfl_up(v, off);
+    if (i >= off) v += u;
+  }
+  return v;
+}
+
+// Largest j < n with pre[j] <= f (pre ascending, pre[0] = 0 <= f)
+__device__ __forceinline__ int lc_find(const int* pre, int n, int f) {
+  int lo = 0, hi = n;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (pre[mid] <= f) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// Per-lane LDS of the tile for the lane-change sub-step
+struct LcTile {
+  const int4* info;  // lane_info of the tile's lanes
+  int* hp;           // queue word (head, parity)
+  int* cnt;          // vehicles
+  int* wo;           // first lattice word (lanes that change lanes)
+  int* vp;           // first vehicle in the tile's vehicle numbering
+  int* mv;           // at a link's lane 0: 1 if any of its vehicles moved
+  uint32_t* lw;      // lead record's xvf word after the sub-step
+  int* lni;          // lead record's route word after the sub-step
+  uint32_t* rw;      // rear record's xvf word after the sub-step
+};
+
+// Lane, record slot and xvf word of vehicle f of the tile's lattice
+// (f < V; lanes in order, each lane lead first)
+__device__ __forceinline__ void lc_locate(const LcTile& T, int nl, int f,
+                                          int& ln, int& slot) {
+  ln = lc_find(T.vp, nl, f);
+  slot = rec_slot(T.info[ln].x, T.hp[ln], lmeta_len((uint32_t)T.info[ln].y),
+                  f - T.vp[ln]);
+}
+
+constexpr int kLcBatch = 4;  // vehicles per thread with loads in flight
+
+// Runs the lane-change sub-step on every link of the tile that changes
+// lanes (every decision on the lattice before the sub-step, then all moves
+// at once).  A link any of whose vehicles moved has its lanes rebuilt, lead
+// first, in the other half of their record double buffer; for those lanes
+// T.hp, T.cnt, T.lw, T.lni and T.rw hold the new state.  Returns the number
+// of vehicles that changed lanes.
+__device__ int lane_change_tile(const DevScen& S, int t, int nl,
+                                const LcTile& T, const LcLat& Z) {
+  const int i = threadIdx.x;
+  GAS v2u* hot = gpv<v2u>(S.hot);
+  GAS v2i* cold = gpv<v2i>(S.cold);
+  int wpl = 0, nv = 0, k = 0;
+  if (i < nl) {
+    const uint32_t meta = (uint32_t)T.info[i].y;
+    if (lmeta_lanes(meta) >= 2) {
+      wpl = (lmeta_len(meta) + 31) >> 5;
+      nv = T.cnt[i];
+      k = lmeta_k(meta);
     }
   }
-  return moves_total;
+  const int wi = wave_incl_scan(wpl), vi = wave_incl_scan(nv);
+  const int Wt = __shfl(wi, kWave - 1), V = __shfl(vi, kWave - 1);
+  if (V == 0) return 0;
+  if (i < nl) {
+    T.wo[i] = wi - wpl;
+    T.vp[i] = vi - nv;
+    T.mv[i] = 0;
+  }
+  for (int q = i; q < Wt; q += kWave) {
+    Z.occ[q] = 0u;
+    Z.rgt[q] = 0u;
+    Z.lft[q] = 0u;
+  }
+  __syncthreads();
+
+  // occupancy
+  for (int f0 = 0; f0 < V; f0 += kLcBatch * kWave) {
+    int ln[kLcBatch], sl[kLcBatch];
+    uint32_t xw[kLcBatch];
+#pragma unroll
+    for (int u = 0; u < kLcBatch; ++u)
+      lc_locate(T, nl, min(f0 + u * kWave + i, V - 1), ln[u], sl[u]);
+#pragma unroll
+    for (int u = 0; u < kLcBatch; ++u) xw[u] = hot[sl[u]].x;
+#pragma unroll
+    for (int u = 0; u < kLcBatch; ++u) {
+      if (f0 + u * kWave + i >= V) continue;
+      const int x = xvf_x(xw[u]);
+      atomicOr(&Z.occ[T.wo[ln[u]] + (x >> 5)], 1u << (x & 31));
+    }
+  }
+  __syncthreads();
+
+  // decisions
+  for (int f0 = 0; f0 < V; f0 += kLcBatch * kWave) {
+    int ln[kLcBatch], sl[kLcBatch];
+    v2u hw[kLcBatch];
+#pragma unroll
+    for (int u = 0; u < kLcBatch; ++u)
+      lc_locate(T, nl, min(f0 + u * kWave + i, V - 1), ln[u], sl[u]);
+#pragma unroll
+    for (int u = 0; u < kLcBatch; ++u) hw[u] = hot[sl[u]];
+#pragma unroll
+    for (int u = 0; u < kLcBatch; ++u) {
+      if (f0 + u * kWave + i >= V) continue;
+      const uint32_t meta = (uint32_t)T.info[ln[u]].y;
+      const int len = lmeta_len(meta), kk = lmeta_k(meta);
+      const int wl = (len + 31) >> 5, q0 = T.wo[ln[u]];
+      const int x = xvf_x(hw[u].x);
+      const int d = lc_decide(S, Z.occ + q0, wl, len, lmeta_lanes(meta), kk,
+                              x, xvf_v(hw[u].x), xvf_fl(hw[u].x),
+                              (int)hw[u].y, t);
+      if (d < 0) continue;
+      atomicOr(d > kk ? &Z.rgt[q0 + (x >> 5)] : &Z.lft[q0 + (x >> 5)],
+               1u << (x & 31));
+    }
+  }
+  __syncthreads();
+
+  // two movers into one cell come from both sides of it: the one from the
+  // lower lane moves, the one moving down stays.  occ becomes the occupancy
+  // after the sub-step.
+  int moved = 0;
+  for (int q = i; q < Wt; q += kWave) {
+    const int ln = lc_find(T.wo, nl, q);
+    const uint32_t meta = (uint32_t)T.info[ln].y;
+    const int kk = lmeta_k(meta), L = lmeta_lanes(meta);
+    const int wl = (lmeta_len(meta) + 31) >> 5;
+    const uint32_t up = Z.rgt[q];
+    const uint32_t below = kk >= 1 ? Z.rgt[q - wl] : 0u;  // k-1 -> k
+    const uint32_t down = Z.lft[q] & ~(kk >= 2 ? Z.rgt[q - 2 * wl] : 0u);
+    const uint32_t above = kk + 1 < L ? Z.lft[q + wl] & ~below : 0u;
+    Z.occ[q] = (Z.occ[q] & ~up & ~down) | below | above;
+    const int m = __popc(up) + __popc(down);
+    if (m) T.mv[ln - kk] = 1;
+    moved += m;
+  }
+  moved = (int)wave_sum((unsigned long long)moved);
+  if (moved == 0) return 0;
+  int carry = 0;
+  for (int q0 = 0; q0 < Wt; q0 += kWave) {
+    const int q = q0 + i;
+    const int c = wave_incl_scan(q < Wt ? __popc(Z.occ[q]) : 0);
+    if (q < Wt) Z.pre[q] = (uint16_t)(carry + c);
+    carry += __shfl(c, kWave - 1);
+  }
+  __syncthreads();
+  const bool mine = wpl > 0 && T.mv[i - k] != 0;
+  if (mine) {
+    const int q0 = T.wo[i];
+    T.cnt[i] = (int)(uint16_t)(Z.pre[q0 + wpl - 1] -
+                               (q0 > 0 ? Z.pre[q0 - 1] : (uint16_t)0));
+  }
+  __syncthreads();
+
+  // rebuild the lanes of the links that moved, lead first
+  for (int f0 = 0; f0 < V; f0 += kLcBatch * kWave) {
+    int ln[kLcBatch], sl[kLcBatch];
+    v2u hw[kLcBatch];
+    v2i cw[kLcBatch];
+#pragma unroll
+    for (int u = 0; u < kLcBatch; ++u)
+      lc_locate(T, nl, min(f0 + u * kWave + i, V - 1), ln[u], sl[u]);
+#pragma unroll
+    for (int u = 0; u < kLcBatch; ++u) {
+      hw[u] = hot[sl[u]];
+      cw[u] = cold[sl[u]];
+    }
+#pragma unroll
+    for (int u = 0; u < kLcBatch; ++u) {
+      if (f0 + u * kWave + i >= V) continue;
+      const uint32_t meta = (uint32_t)T.info[ln[u]].y;
+      const int kk = lmeta_k(meta);
+      if (T.mv[ln[u] - kk] == 0) continue;
+      const int len = lmeta_len(meta), wl = (len + 31) >> 5;
+      const int x = xvf_x(hw[u].x), b = x & 31;
+      const int q = T.wo[ln[u]] + (x >> 5);
+      int d = 0;
+      if ((Z.rgt[q] >> b) & 1u) d = 1;
+      else if (((Z.lft[q] >> b) & 1u) &&
+               !(kk >= 2 && ((Z.rgt[q - 2 * wl] >> b) & 1u)))
+        d = -1;
+      const int lnd = ln[u] + d, qd = q + d * wl;
+      const int j = __popc(b == 31 ? 0u : Z.occ[qd] >> (b + 1)) +
+                    (int)(uint16_t)(Z.pre[T.wo[lnd] + wl - 1] - Z.pre[qd]);
+      if (j >= len) {  // never: a lane holds at most len vehicles
+        atomicOr(S.err, SIM_DEVERR_LANE_FULL);
+        continue;
+      }
+      const int npar = 1 - hc_par(T.hp[ln[u]]);
+      const int dst = T.info[lnd].x + npar * len + j;
+      hot[dst] = hw[u];
+      cold[dst] = cw[u];
+      if (j == 0) {
+        T.lw[lnd] = hw[u].x;
+        T.lni[lnd] = cw[u].y;
+      }
+      if (j == T.cnt[lnd] - 1) T.rw[lnd] = hw[u].x;
+    }
+  }
+  __syncthreads();
+  if (mine) T.hp[i] = hc_make(0, 1 - hc_par(T.hp[i]), 0);
+  return moved;
 }
 
 }  // namespace
@@ -249,6 +390,9 @@ __global__ __launch_bounds__(kWave) void k_front(
   extern __shared__ unsigned char dyn[];
   __shared__ int4 s_info[kMaxTileLanes];
   __shared__ int s_hp[kMaxTileLanes], s_cnt[kMaxTileLanes];
+  __shared__ int s_wo[kMaxTileLanes], s_vp[kMaxTileLanes], s_mv[kMaxTileLanes];
+  __shared__ int s_lni[kMaxTileLanes];
+  __shared__ uint32_t s_lw[kMaxTileLanes], s_rw[kMaxTileLanes];
   __shared__ int4 s_plans[kMaxPlans];
   const long long c0 = wall_clock64();
   const int4 w = work[blockIdx.x];
@@ -350,21 +494,20 @@ __global__ __launch_bounds__(kWave) void k_front(
       s_cnt[i] = cnt;
     }
     __syncthreads();
-    short* lat = reinterpret_cast<short*>(dyn);
-    signed char* dec =
-        reinterpret_cast<signed char*>(dyn) + (size_t)2 * S.lc_cells;
-    lc_moves = lane_change_tile(S, t, nl, s_info, s_hp, s_cnt, lat, dec);
+    const LcTile T{s_info, s_hp, s_cnt, s_wo, s_vp, s_mv, s_lw, s_lni, s_rw};
+    uint32_t* occ = reinterpret_cast<uint32_t*>(dyn);
+    const LcLat Z{occ, occ + S.lc_words, occ + 2 * S.lc_words,
+                  reinterpret_cast<uint16_t*>(occ + 3 * S.lc_words)};
+    lc_moves = lane_change_tile(S, t, nl, T, Z);
     __syncthreads();
     if (act && lc_moves > 0 && hc_make(head, par, 0) != s_hp[i]) {
       head = hc_head(s_hp[i]);
       par = hc_par(s_hp[i]);
       cnt = s_cnt[i];
       if (cnt > 0) {
-        const int hc = hc_make(head, par, 0);
-        const int ls = rec_slot(base, hc, len, 0);
-        lead_w = hot[ls].x;
-        lead_ninfo = cold[ls].y;
-        rear_w = hot[rec_slot(base, hc, len, cnt - 1)].x;
+        lead_w = s_lw[i];
+        lead_ninfo = s_lni[i];
+        rear_w = s_rw[i];
       }
     }
   }
@@ -1316,16 +1459,16 @@ __global__ void k_export_set(const DevScen* d, ExportBufs o, int ring) {
 // ---- launchers -------------------------------------------------------------
 
 hipError_t launch_front(const DevScen* d_descs, int slot, const int4* d_work,
-                        int n_work, int pieces, int step, int lc_cells,
+                        int n_work, int pieces, int step, int lc_words,
                         hipStream_t s) {
   if (n_work <= 0) return hipSuccess;
   (void)hipGetLastError();
   if (slot < 0)
     hipLaunchKernelGGL(k_front<true>, dim3(n_work), dim3(kWave),
-                       (size_t)3 * lc_cells, s, d_descs, 0, d_work, 1, step);
+                       (size_t)kLcBytesPerWord * lc_words, s, d_descs, 0, d_work, 1, step);
   else
     hipLaunchKernelGGL(k_front<false>, dim3(n_work), dim3(kWave),
-                       (size_t)3 * lc_cells, s, d_descs, slot, d_work, pieces,
+                       (size_t)kLcBytesPerWord * lc_words, s, d_descs, slot, d_work, pieces,
                        step);
   return hipGetLastError();
 }

@@ -173,7 +173,7 @@ struct DevScen {
   int32_t lc_desp;
   int32_t n_links, n_tiles, n_ftiles, n_veh;
   int32_t ring_L, ring_n;
-  int32_t lc_cells;  // largest lanes*len of a link that changes lanes
+  int32_t lc_words;  // most lane-change lattice words of one tile
   int64_t n_route;
   const int32_t* link_ext;  // caller's link id, in the internal order
   // lanes: {record base, lmeta, link, end of the link's parking queue}

@@ -21,7 +21,6 @@ using namespace tr;
 
 namespace {
 
-constexpr int kLcMaxLen = 2048;  // longest multi-lane link that changes lanes
 constexpr int kDefaultTileLanes = 16;
 constexpr int kDefaultBackPieces = 4;
 constexpr int kDefaultGraphSteps = 64;
@@ -45,7 +44,7 @@ struct Slot {
   uint64_t ws_bytes = 0, ws_net = 0;
   DevScen d{};
   int32_t t = 0;
-  int32_t lc_cells = 0;
+  int32_t lc_words = 0;
   bool fused = false;  // one kernel per step (state kept by step parity)
   sim_tiling tiling{};
 };
@@ -64,7 +63,7 @@ struct sim_ctx {
   size_t list_cap = 0;
   unsigned long long* d_stats = nullptr;
   std::vector<int32_t> work_key;
-  int n_work = 0, n_net = 0, n_ring = 0, lc_cells = 0;
+  int n_work = 0, n_net = 0, n_ring = 0, lc_words = 0;
   // the work list holds the tiles of fused slots first (n_fwork items, one
   // kernel per step), then those of two-kernel slots
   int n_fwork = 0;
@@ -217,10 +216,6 @@ sim_status check_network(sim_ctx* c, const sim_params* p, const sim_network* n) 
       return fail(c, SIM_E_INVAL, "two links enter node %d with rank %d",
                   n->to[l], n->rank[l]);
     f = 1;
-    if (lc_link(*p, n->lanes[l]) && n->len[l] > kLcMaxLen)
-      return fail(c, SIM_E_CAPACITY,
-                  "link %d: lane changing supports links up to %d cells", l,
-                  kLcMaxLen);
   }
   if (n->signal_plan) {
     if (n->n_plans < 1 || n->n_plans > kMaxPlans)
@@ -418,9 +413,25 @@ extern "C" sim_status sim_load_network(sim_ctx* c, int32_t slot,
     S.fused = !S.ring && c->cfg.step_mode == 0 &&
               !(p->flags & SIM_FLAG_LANE_CHANGE) && min_len >= 2 * p->vmax;
   }
-  S.ftiles = S.fused ? pack_tiles(S.lanes, S.len, c->cfg.tile_lanes, c->cfg.tile_cells)
-                     : pack_tiles(S.lanes, c->cfg.tile_lanes);
+  // one-kernel tiles and tiles of lane-changing links are capped in cells
+  // (the latter bound the lane-change lattice in LDS)
+  const bool lc_slot = !S.ring && (p->flags & SIM_FLAG_LANE_CHANGE);
+  S.ftiles = (S.fused || lc_slot)
+                 ? pack_tiles(S.lanes, S.len, c->cfg.tile_lanes, c->cfg.tile_cells)
+                 : pack_tiles(S.lanes, c->cfg.tile_lanes);
   S.n_ftiles = (int32_t)S.ftiles.size();
+  S.lc_words = 0;
+  if (lc_slot) {
+    int32_t l = 0;
+    for (const int2& tl : S.ftiles) {
+      int32_t words = 0;
+      for (; l < L && S.lane0[l] < tl.x + tl.y; ++l)
+        if (lc_link(*p, S.lanes[l])) words += S.lanes[l] * ((S.len[l] + 31) / 32);
+      S.lc_words = std::max(S.lc_words, words);
+    }
+    if (S.lc_words > kMaxLcWords)
+      return fail(c, SIM_E_CAPACITY, "lane-change lattice of %d words", S.lc_words);
+  }
   S.tiles = S.ftiles;  // the move sub-step splits these tiles further
   S.n_tiles = S.n_ftiles;
   S.tiling = tiling_metrics(S.tiles, S.lanes, S.lane0, S.weight);
@@ -449,8 +460,6 @@ extern "C" sim_status sim_load_network(sim_ctx* c, int32_t slot,
   int64_t rec = 0;
   for (int32_t i = 0; i < L; ++i) {
     const int cap = S.len[i] * (lc_link(*p, S.lanes[i]) ? 2 : 1);
-    if (lc_link(*p, S.lanes[i]))
-      S.lc_cells = std::max(S.lc_cells, S.lanes[i] * S.len[i]);
     S.base[i] = (int32_t)rec;
     const int rank = S.ring ? 0 : net->rank[order[i]];
     for (int k = 0; k < S.lanes[i]; ++k) {
@@ -490,7 +499,7 @@ extern "C" sim_status sim_load_network(sim_ctx* c, int32_t slot,
   d.xcap = (S.ring || S.fused) ? 0 : (int32_t)extra_cap(S.n_ftiles, c->cfg.back_pieces);
   d.n_plans = (!S.ring && net->signal_plan) ? net->n_plans : 0;
   d.fused = S.fused ? 1 : 0;
-  d.lc_cells = S.lc_cells;
+  d.lc_words = S.lc_words;
   d.ring_L = S.ring ? net->len[0] : 0;
   hipStream_t s = c->stream;
   HIPCHK(c, up(const_cast<int32_t*>(d.link_ext), S.ext_of.data(), L, s));
@@ -801,7 +810,7 @@ sim_status build_work(sim_ctx* c, const std::vector<int32_t>& net,
       if (S.fused != (pass == 0)) continue;
       (pass == 0 ? fused_slots : two_slots).push_back(sl);
       for (int32_t t = 0; t < S.n_ftiles; ++t) all.push_back(make_int2(sl, t));
-      if (pass == 1) lc = std::max(lc, S.lc_cells);
+      if (pass == 1) lc = std::max(lc, S.lc_words);
     }
     const std::vector<int2> dealt = xcd_interleave(all, 8);
     for (size_t k = 0; k < dealt.size(); ++k) {
@@ -843,7 +852,7 @@ sim_status build_work(sim_ctx* c, const std::vector<int32_t>& net,
   c->n_work = (int)work.size();
   c->n_net = (int)net.size();
   c->n_ring = (int)ring.size();
-  c->lc_cells = lc;
+  c->lc_words = lc;
   c->work_key = key;
   return SIM_OK;
 }
@@ -914,7 +923,8 @@ sim_status build_graph(sim_ctx* c, int K, bool profiled, hipGraphExec_t* out) {
     }
     if (n_tw > 0) {
       void* fa[] = {&descs, &slot, &work, &pieces, &step};
-      add(front_kernel(batched), n_tw, kFrontThreads, (size_t)3 * c->lc_cells, fa);
+      add(front_kernel(batched), n_tw, kFrontThreads,
+          (size_t)kLcBytesPerWord * c->lc_words, fa);
       mark(0);
       void* ba[] = {&descs, &slot, &work, &n_work, &step};
       add(back_kernel(batched), n_tw + (batched ? 0 : c->n_extra),
@@ -1083,7 +1093,7 @@ extern "C" sim_status sim_step(sim_ctx* c, const int32_t* slots, int32_t n_slots
       if (n_tw > 0) {
         st = timed(c, 0, [&] {
           return launch_front(c->d_descs, c->single_slot, c->d_work + n_fw, n_tw,
-                              c->cfg.back_pieces, s, c->lc_cells, c->stream);
+                              c->cfg.back_pieces, s, c->lc_words, c->stream);
         });
         if (st != SIM_OK) return st;
         st = timed(c, 1, [&] {

@@ -1,7 +1,9 @@
 """Edge cases of the network step on the GPU, in both step modes, against
 the CPU oracle: extreme speeds and slowdown probabilities, every vehicle
 departing at once, four lanes everywhere, the longest links the library
-accepts, the smallest grid, and a scenario with no vehicles at all."""
+accepts (also with lane changes, whose bit lattice of a 4-lane link of
+32,767 cells takes 4,096 words of LDS), the smallest grid, and a scenario
+with no vehicles at all."""
 import numpy as np
 import pytest
 
@@ -62,6 +64,34 @@ def test_longest_links(mode):
     assert scen.link_len.max() <= 32767
     ctx = _ctx(mode)
     run_side_by_side(ctx, 0, scen, 200, every=100)
+    ctx.close()
+
+
+@pytest.mark.parametrize("tile_cells", [0, 64])
+def test_lane_changes_on_the_longest_links(tile_cells):
+    # 4-lane links of 30,000-32,767 cells with lane changes and turn lanes:
+    # each tile holds one link (tile_cells caps the tiles in cells)
+    def lengths(rng, m):
+        return rng.integers(30000, 32768, size=m)
+    scen = S.grid_scenario(3, 3, 16, 400, T=150, depart_max=40, seed=17,
+                           len_sampler=lengths, lanes_range=(4, 4),
+                           flags=S.FLAG_LANE_CHANGE | S.FLAG_TURN_LANES)
+    ctx = _ctx(1, tile_cells=tile_cells)
+    o = run_side_by_side(ctx, 0, scen, 150, every=50, full_at=(75,))
+    assert o.stats()["lane_changes"] > 0
+    ctx.close()
+
+
+@pytest.mark.parametrize("tile_lanes", [64, 8])
+def test_lane_changes_in_a_jam(tile_lanes):
+    # every vehicle released at t = 0 onto short 2-4 lane links: many
+    # vehicles per tile (several batches of the lane-change pass)
+    scen = S.grid_scenario(4, 5, 40, 6000, T=200, depart_max=0, seed=18,
+                           lanes_range=(2, 4),
+                           flags=S.FLAG_LANE_CHANGE | S.FLAG_TURN_LANES)
+    ctx = _ctx(1, tile_lanes=tile_lanes, tile_cells=65536)
+    o = run_side_by_side(ctx, 0, scen, 200, every=20, full_at=(1, 2, 100))
+    assert o.stats()["lane_changes"] > 0
     ctx.close()
 
 
