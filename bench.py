@@ -363,6 +363,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--workload", default="portland")
     ap.add_argument("--tile-lanes", type=int, default=0)
+    ap.add_argument("--tile-cells", type=int, default=0)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--reps", type=int, default=5,
@@ -391,7 +392,8 @@ def main():
         return bench_serve(args)
     log(f"bench: generating workload {args.workload}")
     scen, cfg = make_workload(args.workload, args.steps)
-    ctx = Context(max_slots=2, tile_lanes=args.tile_lanes)
+    ctx = Context(max_slots=2, tile_lanes=args.tile_lanes,
+                  tile_cells=args.tile_cells)
 
     # warm-up on a throw-away copy, then a fresh load for the timed run
     log(f"bench: warmup {args.warmup} steps")

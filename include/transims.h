@@ -73,7 +73,8 @@ typedef struct {
   int32_t max_slots;   /* number of independent scenario slots (>= 1)       */
   void* stream;        /* hipStream_t for all device work; NULL = default   */
   int32_t tile_lanes;   /* lanes per workgroup tile (whole links), 1..64;
-                           0 = default (16)                                 */
+                           0 = default (16; 32 for scenarios with lane
+                           changes)                                         */
   int32_t back_pieces;  /* wavefronts per tile in the move sub-step, which
                            share the tile's lanes by vehicle load, 1..8;
                            0 = default (4)                                  */

@@ -209,7 +209,67 @@ __device__ __forceinline__ void lc_locate(const LcTile& T, int nl, int f,
                   f - T.vp[ln]);
 }
 
-constexpr int kLcBatch = 4;  // vehicles per thread with loads in flight
+// Vehicles per thread whose records stay in registers through the
+// sub-step (the tile's first kLcRes * kWave vehicles: one round of loads);
+// the rest are loaded again by each phase, kLcBatch per thread at a time.
+constexpr int kLcRes = 2;
+constexpr int kLcBatch = 2;
+
+__device__ __forceinline__ void lc_mark_occ(const LcTile& T, const LcLat& Z,
+                                            int ln, uint32_t xw) {
+  const int x = xvf_x(xw);
+  atomicOr(&Z.occ[T.wo[ln] + (x >> 5)], 1u << (x & 31));
+}
+
+__device__ __forceinline__ void lc_mark_move(const DevScen& S, const LcTile& T,
+                                             const LcLat& Z, int t, int ln,
+                                             v2u hw) {
+  const uint32_t meta = (uint32_t)T.info[ln].y;
+  const int len = lmeta_len(meta), k = lmeta_k(meta);
+  const int wl = (len + 31) >> 5, q0 = T.wo[ln];
+  const int x = xvf_x(hw.x);
+  const int d = lc_decide(S, Z.occ + q0, wl, len, lmeta_lanes(meta), k, x,
+                          xvf_v(hw.x), xvf_fl(hw.x), (int)hw.y, t);
+  if (d < 0) return;
+  atomicOr(d > k ? &Z.rgt[q0 + (x >> 5)] : &Z.lft[q0 + (x >> 5)],
+           1u << (x & 31));
+}
+
+// Writes the vehicle's records at its place in its lane after the sub-step
+// (links with a move only).
+__device__ __forceinline__ void lc_place(const DevScen& S, const LcTile& T,
+                                         const LcLat& Z, int ln, v2u hw,
+                                         v2i cw) {
+  const uint32_t meta = (uint32_t)T.info[ln].y;
+  const int k = lmeta_k(meta);
+  if (T.mv[ln - k] == 0) return;
+  const int len = lmeta_len(meta), wl = (len + 31) >> 5;
+  const int x = xvf_x(hw.x), b = x & 31;
+  const int q = T.wo[ln] + (x >> 5);
+  int d = 0;
+  if ((Z.rgt[q] >> b) & 1u) d = 1;
+  else if (((Z.lft[q] >> b) & 1u) &&
+           !(k >= 2 && ((Z.rgt[q - 2 * wl] >> b) & 1u)))
+    d = -1;
+  const int lnd = ln + d, qd = q + d * wl;
+  const int j = __popc(b == 31 ? 0u : Z.occ[qd] >> (b + 1)) +
+                (int)(uint16_t)(Z.pre[T.wo[lnd] + wl - 1] - Z.pre[qd]);
+  if (j >= len) {  // never: a lane holds at most len vehicles
+    atomicOr(S.err, SIM_DEVERR_LANE_FULL);
+    return;
+  }
+  const int npar = 1 - hc_par(T.hp[ln]);
+  const int dst = T.info[lnd].x + npar * len + j;
+  GAS v2u* hot = gpv<v2u>(S.hot);
+  GAS v2i* cold = gpv<v2i>(S.cold);
+  hot[dst] = hw;
+  cold[dst] = cw;
+  if (j == 0) {
+    T.lw[lnd] = hw.x;
+    T.lni[lnd] = cw.y;
+  }
+  if (j == T.cnt[lnd] - 1) T.rw[lnd] = hw.x;
+}
 
 // Runs the lane-change sub-step on every link of the tile that changes
 // lanes (every decision on the lattice before the sub-step, then all moves
@@ -246,8 +306,29 @@ __device__ int lane_change_tile(const DevScen& S, int t, int nl,
   }
   __syncthreads();
 
+  // the first kLcRes * kWave vehicles, loaded once (threads past V load the
+  // last vehicle and drop it)
+  int rln[kLcRes];
+  v2u rhw[kLcRes];
+  v2i rcw[kLcRes];
+  {
+    int rsl[kLcRes];
+#pragma unroll
+    for (int u = 0; u < kLcRes; ++u)
+      lc_locate(T, nl, min(u * kWave + i, V - 1), rln[u], rsl[u]);
+#pragma unroll
+    for (int u = 0; u < kLcRes; ++u) {
+      rhw[u] = hot[rsl[u]];
+      rcw[u] = cold[rsl[u]];
+    }
+  }
+  const int f_rest = kLcRes * kWave;  // first vehicle of the loops below
+
   // occupancy
-  for (int f0 = 0; f0 < V; f0 += kLcBatch * kWave) {
+#pragma unroll
+  for (int u = 0; u < kLcRes; ++u)
+    if (u * kWave + i < V) lc_mark_occ(T, Z, rln[u], rhw[u].x);
+  for (int f0 = f_rest; f0 < V; f0 += kLcBatch * kWave) {
     int ln[kLcBatch], sl[kLcBatch];
     uint32_t xw[kLcBatch];
 #pragma unroll
@@ -256,16 +337,16 @@ __device__ int lane_change_tile(const DevScen& S, int t, int nl,
 #pragma unroll
     for (int u = 0; u < kLcBatch; ++u) xw[u] = hot[sl[u]].x;
 #pragma unroll
-    for (int u = 0; u < kLcBatch; ++u) {
-      if (f0 + u * kWave + i >= V) continue;
-      const int x = xvf_x(xw[u]);
-      atomicOr(&Z.occ[T.wo[ln[u]] + (x >> 5)], 1u << (x & 31));
-    }
+    for (int u = 0; u < kLcBatch; ++u)
+      if (f0 + u * kWave + i < V) lc_mark_occ(T, Z, ln[u], xw[u]);
   }
   __syncthreads();
 
   // decisions
-  for (int f0 = 0; f0 < V; f0 += kLcBatch * kWave) {
+#pragma unroll
+  for (int u = 0; u < kLcRes; ++u)
+    if (u * kWave + i < V) lc_mark_move(S, T, Z, t, rln[u], rhw[u]);
+  for (int f0 = f_rest; f0 < V; f0 += kLcBatch * kWave) {
     int ln[kLcBatch], sl[kLcBatch];
     v2u hw[kLcBatch];
 #pragma unroll
@@ -274,19 +355,8 @@ __device__ int lane_change_tile(const DevScen& S, int t, int nl,
 #pragma unroll
     for (int u = 0; u < kLcBatch; ++u) hw[u] = hot[sl[u]];
 #pragma unroll
-    for (int u = 0; u < kLcBatch; ++u) {
-      if (f0 + u * kWave + i >= V) continue;
-      const uint32_t meta = (uint32_t)T.info[ln[u]].y;
-      const int len = lmeta_len(meta), kk = lmeta_k(meta);
-      const int wl = (len + 31) >> 5, q0 = T.wo[ln[u]];
-      const int x = xvf_x(hw[u].x);
-      const int d = lc_decide(S, Z.occ + q0, wl, len, lmeta_lanes(meta), kk,
-                              x, xvf_v(hw[u].x), xvf_fl(hw[u].x),
-                              (int)hw[u].y, t);
-      if (d < 0) continue;
-      atomicOr(d > kk ? &Z.rgt[q0 + (x >> 5)] : &Z.lft[q0 + (x >> 5)],
-               1u << (x & 31));
-    }
+    for (int u = 0; u < kLcBatch; ++u)
+      if (f0 + u * kWave + i < V) lc_mark_move(S, T, Z, t, ln[u], hw[u]);
   }
   __syncthreads();
 
@@ -327,7 +397,10 @@ __device__ int lane_change_tile(const DevScen& S, int t, int nl,
   __syncthreads();
 
   // rebuild the lanes of the links that moved, lead first
-  for (int f0 = 0; f0 < V; f0 += kLcBatch * kWave) {
+#pragma unroll
+  for (int u = 0; u < kLcRes; ++u)
+    if (u * kWave + i < V) lc_place(S, T, Z, rln[u], rhw[u], rcw[u]);
+  for (int f0 = f_rest; f0 < V; f0 += kLcBatch * kWave) {
     int ln[kLcBatch], sl[kLcBatch];
     v2u hw[kLcBatch];
     v2i cw[kLcBatch];
@@ -340,36 +413,8 @@ __device__ int lane_change_tile(const DevScen& S, int t, int nl,
       cw[u] = cold[sl[u]];
     }
 #pragma unroll
-    for (int u = 0; u < kLcBatch; ++u) {
-      if (f0 + u * kWave + i >= V) continue;
-      const uint32_t meta = (uint32_t)T.info[ln[u]].y;
-      const int kk = lmeta_k(meta);
-      if (T.mv[ln[u] - kk] == 0) continue;
-      const int len = lmeta_len(meta), wl = (len + 31) >> 5;
-      const int x = xvf_x(hw[u].x), b = x & 31;
-      const int q = T.wo[ln[u]] + (x >> 5);
-      int d = 0;
-      if ((Z.rgt[q] >> b) & 1u) d = 1;
-      else if (((Z.lft[q] >> b) & 1u) &&
-               !(kk >= 2 && ((Z.rgt[q - 2 * wl] >> b) & 1u)))
-        d = -1;
-      const int lnd = ln[u] + d, qd = q + d * wl;
-      const int j = __popc(b == 31 ? 0u : Z.occ[qd] >> (b + 1)) +
-                    (int)(uint16_t)(Z.pre[T.wo[lnd] + wl - 1] - Z.pre[qd]);
-      if (j >= len) {  // never: a lane holds at most len vehicles
-        atomicOr(S.err, SIM_DEVERR_LANE_FULL);
-        continue;
-      }
-      const int npar = 1 - hc_par(T.hp[ln[u]]);
-      const int dst = T.info[lnd].x + npar * len + j;
-      hot[dst] = hw[u];
-      cold[dst] = cw[u];
-      if (j == 0) {
-        T.lw[lnd] = hw[u].x;
-        T.lni[lnd] = cw[u].y;
-      }
-      if (j == T.cnt[lnd] - 1) T.rw[lnd] = hw[u].x;
-    }
+    for (int u = 0; u < kLcBatch; ++u)
+      if (f0 + u * kWave + i < V) lc_place(S, T, Z, ln[u], hw[u], cw[u]);
   }
   __syncthreads();
   if (mine) T.hp[i] = hc_make(0, 1 - hc_par(T.hp[i]), 0);

@@ -22,6 +22,9 @@ using namespace tr;
 namespace {
 
 constexpr int kDefaultTileLanes = 16;
+// scenarios with lane changes: the lane-change sub-step favours fewer,
+// larger tiles than the move sub-step alone
+constexpr int kDefaultLcTileLanes = 32;
 constexpr int kDefaultBackPieces = 4;
 constexpr int kDefaultGraphSteps = 64;
 // one-kernel steps: a tile also stops at this many cells, so that no
@@ -295,7 +298,6 @@ extern "C" sim_status sim_create(const sim_config* cfg, sim_ctx** out) {
   sim_ctx* c = new (std::nothrow) sim_ctx();
   if (!c) return SIM_E_CAPACITY;
   c->cfg = *cfg;
-  if (c->cfg.tile_lanes == 0) c->cfg.tile_lanes = kDefaultTileLanes;
   if (c->cfg.back_pieces == 0) c->cfg.back_pieces = kDefaultBackPieces;
   if (c->cfg.graph_steps == 0) c->cfg.graph_steps = kDefaultGraphSteps;
   if (c->cfg.tile_cells == 0) c->cfg.tile_cells = kDefaultTileCells;
@@ -416,9 +418,12 @@ extern "C" sim_status sim_load_network(sim_ctx* c, int32_t slot,
   // one-kernel tiles and tiles of lane-changing links are capped in cells
   // (the latter bound the lane-change lattice in LDS)
   const bool lc_slot = !S.ring && (p->flags & SIM_FLAG_LANE_CHANGE);
+  const int tile_lanes = c->cfg.tile_lanes != 0 ? c->cfg.tile_lanes
+                         : lc_slot              ? kDefaultLcTileLanes
+                                                : kDefaultTileLanes;
   S.ftiles = (S.fused || lc_slot)
-                 ? pack_tiles(S.lanes, S.len, c->cfg.tile_lanes, c->cfg.tile_cells)
-                 : pack_tiles(S.lanes, c->cfg.tile_lanes);
+                 ? pack_tiles(S.lanes, S.len, tile_lanes, c->cfg.tile_cells)
+                 : pack_tiles(S.lanes, tile_lanes);
   S.n_ftiles = (int32_t)S.ftiles.size();
   S.lc_words = 0;
   if (lc_slot) {
