@@ -1,8 +1,8 @@
 """Summaries of rocprofv3 output for the step kernels.
 
-    python -m paper_cs_0105004_amd.profiling stats  <run_kernel_stats.csv>
-    python -m paper_cs_0105004_amd.profiling pmc    <run_counter_collection.csv> [LAST]
-    python -m paper_cs_0105004_amd.profiling copy   <run_counter_collection.csv> BYTES
+    python -m paper_cs_0105004_amd.profiling stats  <run_kernel_stats.csv | run_results.db>
+    python -m paper_cs_0105004_amd.profiling pmc    <run_counter_collection.csv | run_results.db> [LAST]
+    python -m paper_cs_0105004_amd.profiling copy   <run_counter_collection.csv | run_results.db> BYTES
 
 `stats` prints calls / average / total duration per kernel from a
 `--kernel-trace --stats` run; `pmc` prints, per kernel, the dispatch count and
@@ -10,11 +10,13 @@ the mean of every collected counter per dispatch (FETCH_SIZE and WRITE_SIZE
 are in KiB), over the LAST dispatches of each kernel if given; `copy` prints
 the bytes one plain copy of BYTES bytes reads and writes according to those
 counters, i.e. the calibration factor that turns the counters of the step
-kernels into HBM bytes.
+kernels into HBM bytes.  Each reads rocprofv3's CSV output or its SQLite
+database (`run_results.db`, the default output format).
 """
 from __future__ import annotations
 
 import csv
+import sqlite3
 import sys
 from collections import defaultdict
 
@@ -29,6 +31,16 @@ def short_name(name: str) -> str:
 
 def kernel_stats(path: str) -> dict:
     out = {}
+    if path.endswith(".db"):
+        db = sqlite3.connect(path)
+        rows = db.execute("select name, count(*), avg(duration), sum(duration),"
+                          " min(duration), max(duration) from kernels"
+                          " group by name").fetchall()
+        for name, n, avg, tot, mn, mx in rows:
+            out[short_name(name)] = {"calls": int(n), "avg_ns": float(avg),
+                                     "total_ns": float(tot),
+                                     "min_ns": float(mn), "max_ns": float(mx)}
+        return out
     with open(path, newline="") as f:
         for row in csv.DictReader(f):
             out[short_name(row["Name"])] = {
@@ -44,10 +56,17 @@ def counters(path: str, last: int = 0) -> dict:
     """{kernel: {counter: (dispatches, mean per dispatch)}}, over the `last`
     dispatches of each kernel (in dispatch order) when last > 0."""
     vals = defaultdict(lambda: defaultdict(list))
-    with open(path, newline="") as f:
-        for row in csv.DictReader(f):
-            vals[short_name(row["Kernel_Name"])][row["Counter_Name"]].append(
-                (int(row["Dispatch_Id"]), float(row["Counter_Value"])))
+    if path.endswith(".db"):
+        db = sqlite3.connect(path)
+        for kn, cn, did, v in db.execute(
+                "select kernel_name, counter_name, dispatch_id, value"
+                " from counters_collection"):
+            vals[short_name(kn)][cn].append((int(did), float(v)))
+    else:
+        with open(path, newline="") as f:
+            for row in csv.DictReader(f):
+                vals[short_name(row["Kernel_Name"])][row["Counter_Name"]].append(
+                    (int(row["Dispatch_Id"]), float(row["Counter_Value"])))
     out = {}
     for k, cs in vals.items():
         out[k] = {}
