@@ -30,7 +30,7 @@ constexpr int kRingBlock = 256;
 // load of a lane in the move sub-step: its vehicles plus a fixed cost; a
 // tile gets one move wavefront per kPieceCost of load (up to a limit)
 constexpr int kLaneCost = 4;
-constexpr int kPieceCost = 256;
+constexpr int kPieceCost = 512;
 
 // Pointers read from a descriptor are generic; casting them to the global
 // address space lets the compiler use global (not flat) memory instructions,
