@@ -87,28 +87,47 @@ def algorithmic_bytes(kind, st):
     return 2.0 * st["c_occ"] + 8.0 * st["veh_updates"]  # ring: one launch
 
 
-KERNEL_SOURCES = ("kernels.hip", "kernels.h", "layout.h", "philox.h")
+# the sources each kernel family compiles from: a family's digest changes
+# only when its own code (or a shared header) does
+_SHARED = ("device.h", "kernels.h", "layout.h", "philox.h")
+KERNEL_SOURCES = {"step": ("step.hip",) + _SHARED,
+                  "front_back": ("front_back.hip",) + _SHARED,
+                  "ring": ("ring_stats.hip",) + _SHARED}
+FAMILY = {"step": "step", "front": "front_back", "back": "front_back",
+          "ring": "ring"}
 
 
-def kernel_digest() -> str:
+def kernel_digest(family: str = "step") -> str:
     import hashlib
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in KERNEL_SOURCES[family]:
         with open(os.path.join(ROOT, "paper_cs_0105004_amd", "csrc", f),
                   "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-# HBM bytes per launch of the move kernel on the default workload, from
-# rocprofv3 FETCH_SIZE and WRITE_SIZE (KiB per dispatch, mean over the run)
-# scaled by what the same counters read for a plain copy of known size.
-# Valid only for the kernel sources with this digest.
+def family_of(kinds) -> str:
+    """Kernel family of the step kernels that ran ("front"/"back" together
+    are the two-kernel family)."""
+    fams = {FAMILY[k] for k in kinds}
+    return fams.pop() if len(fams) == 1 else "front_back"
+
+
+# HBM bytes per launch of the step kernel, by workload, from rocprofv3
+# FETCH_SIZE and WRITE_SIZE (KiB per dispatch, mean over the timed run)
+# scaled by what the same counters read for a plain copy of known size
+# (x 2.0 and x 1.0).  Valid only for the kernel sources with this digest
+# (of the kernel's family).
 MEASURED_TRAFFIC = {
-    # k_step: FETCH 2589.6 KiB x 2.0 + WRITE 2577.9 KiB x 1.0 per dispatch
-    "e245032d36d9eda8": {"kernel": "step", "steps": 3600,
-                         "bytes_per_launch": 7757.1 * 1024},
 }
+
+
+def measured_traffic(family: str, workload: str, steps: int):
+    tr = MEASURED_TRAFFIC.get(kernel_digest(family), {}).get(workload)
+    if tr is None or tr["steps"] != steps:
+        return None
+    return tr["bytes_per_launch"]
 
 
 def copy_calibration(nbytes: int, reps: int = 5):
@@ -145,7 +164,7 @@ def cpu_baseline(scen, budget_s: float):
                       f"single thread)"}
 
 
-def roofline_from(kt, stats_list, region_ms=None, digest=None):
+def roofline_from(kt, stats_list, region_ms=None, workload=None, steps=None):
     """Roofline object of the dominant step kernel from per-kernel times and
     the summed counters of the scenarios it processed.  With one step kernel
     and the event time of the timed region, the launch duration is that
@@ -170,12 +189,15 @@ def roofline_from(kt, stats_list, region_ms=None, digest=None):
         timing = "event nodes between kernels (corrected)"
     bytes_launch = algorithmic_bytes(dom, tot) / launches
     achieved = bytes_launch / (avg_ms * 1e-3) / 1e9
+    fam = family_of(kinds)
     return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+            "traffic": (measured_traffic(fam, workload, steps)
+                        if workload else None),
             "kernel": name, "avg_launch_us": avg_ms * 1e3,
             "timing": timing,
             "algorithmic_bytes_per_launch": bytes_launch,
-            "kernel_sources_digest": digest or kernel_digest(),
+            "kernel_sources_digest": kernel_digest(fam),
             "kernel_ms": {k: kt[k][1] for k in kinds},
             "launches": {k: kt[k][0] for k in kinds}}
 
@@ -254,7 +276,8 @@ def bench_batched(args):
     ctx.profile(False)
     for k in slots:
         assert ctx.stats(k)["hash"] == stats[k]["hash"], "replay diverged"
-    roof = roofline_from(kt, stats, region_ms)
+    roof = roofline_from(kt, stats, region_ms, workload="batched",
+                         steps=args.steps)
     ctx.close()
     log("bench: plain loop")
     plain = Context(max_slots=1, graph_steps=-1)
@@ -455,12 +478,9 @@ def main():
             timing += " (lane-change and move kernels together)"
         bytes_launch = algorithmic_bytes(dom, st) / launches
         achieved = bytes_launch / (avg_ms * 1e-3) / 1e9
-        digest = kernel_digest()
-        traffic = None
-        tr = MEASURED_TRAFFIC.get(digest)
-        if tr is not None and args.workload == "portland" and \
-                args.steps == tr["steps"] and dom == tr["kernel"]:
-            traffic = tr["bytes_per_launch"]
+        fam = family_of(kinds)
+        digest = kernel_digest(fam)
+        traffic = measured_traffic(fam, args.workload, args.steps)
         roof = {"bound": "hbm", "achieved": achieved,
                 "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,

@@ -9,7 +9,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libtransims.so")
-SOURCES = ["csrc/transims.cpp", "csrc/tiler.cpp", "csrc/kernels.hip"]
+SOURCES = ["csrc/transims.cpp", "csrc/tiler.cpp", "csrc/step.hip",
+           "csrc/front_back.hip", "csrc/ring_stats.hip"]
 ARCH = "gfx950"
 
 

@@ -1,4 +1,5 @@
-// kernels.hip -- gfx950 kernels of the TRANSIMS per-second update.
+// front_back.hip -- the two-kernel form of the TRANSIMS per-second update
+// (gfx950), used with lane changes or short links.
 //
 // A step is two kernels, the GPU form of the paper's update sequence
 // "change lanes / exchange / compute speeds and move / exchange" (Section
@@ -18,6 +19,7 @@
 //            brake to the gap, slow down at random and move every vehicle;
 //            the lead vehicle that passes the node is written to the handoff
 //            slot of its target lane (at most one per lane and step).
+#include "device.h"
 #include "kernels.h"
 #include "philox.h"
 #include "transims.h"
@@ -26,61 +28,10 @@ namespace tr {
 
 namespace {
 
-constexpr int kRingBlock = 256;
 // load of a lane in the move sub-step: its vehicles plus a fixed cost; a
 // tile gets one move wavefront per kPieceCost of load (up to a limit)
 constexpr int kLaneCost = 4;
 constexpr int kPieceCost = 512;
-
-// Pointers read from a descriptor are generic; casting them to the global
-// address space lets the compiler use global (not flat) memory instructions,
-// whose completion is tracked apart from LDS traffic.
-// HIP's vector classes cannot be copied out of that address space, so the
-// kernels use the compiler's own vector types there.
-#define GAS __attribute__((address_space(1)))
-typedef int v2i __attribute__((ext_vector_type(2)));
-typedef int v4i __attribute__((ext_vector_type(4)));
-typedef unsigned v2u __attribute__((ext_vector_type(2)));
-template <class T>
-__device__ __forceinline__ GAS T* gp(T* p) {
-  return (GAS T*)p;
-}
-template <class V, class T>
-__device__ __forceinline__ GAS V* gpv(T* p) {
-  return (GAS V*)(void*)p;
-}
-
-__device__ __forceinline__ int wrapi(int a, int cap) {
-  return a >= cap ? a - cap : a;
-}
-
-// record slot of the j-th vehicle (0 = lead) of a lane with queue word hc
-__device__ __forceinline__ int rec_slot(int base, int hc, int len, int j) {
-  return base + hc_par(hc) * len + wrapi(hc_head(hc) + j, len);
-}
-
-// Is the fixed-time signal at the end of the lane's link red in step t?
-// (a virtual vehicle of speed zero then stands beyond the last cell)
-__device__ __forceinline__ bool sig_red(const int4* s_plans, uint32_t meta,
-                                        int t) {
-  const int pl = lmeta_plan(meta);
-  if (pl < 0) return false;
-  const int4 q = s_plans[pl];
-  return (int)(((uint32_t)t + (uint32_t)q.z) % (uint32_t)q.x) < q.y;
-}
-
-// The scenario's signal plans into LDS (thread j takes plan j); the caller
-// orders the writes before their first use.
-__device__ __forceinline__ void load_plans(const DevScen& S, int4* s_plans) {
-  const int i = threadIdx.x;
-  if (i < S.n_plans) s_plans[i] = S.plans[i];
-}
-
-__device__ __forceinline__ unsigned long long wave_sum(unsigned long long v) {
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
-  return v;
-}
 
 // ---- lane change on one tile ------------------------------------------
 // The lane-change sub-step of a tile works on bit lattices in LDS, one bit
@@ -423,6 +374,7 @@ __device__ int lane_change_tile(const DevScen& S, int t, int nl,
 
 }  // namespace
 
+
 // ---------------------------------------------------------------------------
 // Work items are {slot, first lane, lanes, tile}.  With kBatched false every
 // item belongs to slot `slot`, whose descriptor is then read without waiting
@@ -604,14 +556,6 @@ __global__ __launch_bounds__(kWave) void k_front(
   }
 }
 
-// Orders this lane's LDS accesses before the next ones of any lane of the
-// wavefront: a wavefront executes its LDS instructions in order, so keeping
-// the compiler from moving them is enough, and nothing waits on memory.
-__device__ __forceinline__ void wave_lds_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-}
-
 // The back kernel: one wavefront per tile of at most 64 lanes, plus the
 // extra wavefronts the front kernel listed for heavy tiles.  The wavefronts
 // of a tile cut it into as many contiguous runs of lanes of about equal load
@@ -619,7 +563,6 @@ __device__ __forceinline__ void wave_lds_sync() {
 // load, redone every step from the current counts -- and each takes one run.
 // Lane threads resolve the intersections, then the vehicles of the run are
 // updated 64 at a time.
-constexpr int kGroup = 2;  // chunks of 64 vehicles loaded before updating
 
 template <bool kBatched>
 __global__ __launch_bounds__(kWave) void k_back(
@@ -868,641 +811,10 @@ __global__ __launch_bounds__(kWave) void k_back(
   }
 }
 
-// ---------------------------------------------------------------------------
-// The move of one group of kGroup x 64 vehicles in the one-kernel step:
-// step_load reads what the group needs (vehicle records from the lanes'
-// rings, or from LDS for the vehicles that arrived in this step),
-// step_run updates the group.
-struct StepGroup {
-  v2u hw[kGroup];
-  v2i cw[kGroup];
-  uint32_t ahead[kGroup];
-  int sl[kGroup], lij[kGroup];
-};
-struct StepCtx {
-  int t, vmax;
-  uint32_t key0, key1;
-  uint64_t slow_thr;
-};
-
-__device__ __forceinline__ void step_load(
-    StepGroup& G, int g0, int i, int total, int nl, const int* s_pre,
-    const int* s_len, const int* s_base, const int* s_hp, GAS v2u* hot,
-    GAS uint32_t* hot_w, GAS v2i* cold) {
-#pragma unroll
-  for (int c = 0; c < kGroup; ++c) {
-    const int fr = (g0 + c) * kWave + i;
-    const int f = max(min(fr, total - 1), 0);
-    int lo = 0, hi = nl;
-    while (hi - lo > 1) {
-      const int mid = (lo + hi) >> 1;
-      if (s_pre[mid] <= f) lo = mid;
-      else hi = mid;
-    }
-    const int j = f - s_pre[lo];
-    const int llen = s_len[lo], lbase = s_base[lo], lhp = s_hp[lo];
-    G.sl[c] = rec_slot(lbase, lhp, llen, j);
-    // ring slots are loaded for every vehicle (an arrival's slot holds a
-    // stale record, which step_run replaces from LDS), so no load sits in
-    // a branch
-    const int sa = j > 0 ? rec_slot(lbase, lhp, llen, j - 1) : G.sl[c];
-    const int sc = j <= 1 ? G.sl[c] : rec_slot(lbase, lhp, llen, 0);
-    G.hw[c] = hot[G.sl[c]];
-    G.ahead[c] = hot_w[2 * sa];
-    G.cw[c] = cold[sc];
-    G.lij[c] = (fr < total) ? (lo | (j << 8)) : -1;
-  }
-}
-
-__device__ __forceinline__ void step_run(
-    const StepGroup& G, const StepCtx& cx, const int* s_len, const int* s_cnt0,
-    const int* s_pre, const int* s_extra, const int* s_tgt,
-    const uint2 (*s_nhot)[2], const int2 (*s_ncold)[2], int4* s_ends,
-    int2* s_second, int* s_left, GAS v2u* hot, GAS uint32_t* hot_w,
-    GAS v2i* cold, const GAS uint32_t* __restrict__ route_info,
-    GAS int32_t* __restrict__ exit_t, GAS v4i* __restrict__ ha_out,
-    GAS int32_t* __restrict__ hb_out, GAS int32_t* __restrict__ ht_out,
-    unsigned long long& sumv, unsigned long long& cross,
-    unsigned long long& exits) {
-#pragma unroll
-  for (int c = 0; c < kGroup; ++c) {
-    if (G.lij[c] < 0) continue;
-    const int li = G.lij[c] & 0xFF, j = G.lij[c] >> 8;
-    const int llen = s_len[li];
-    const int c0l = s_cnt0[li];
-    v2u hw = G.hw[c];
-    v2i cw = G.cw[c];
-    uint32_t ahead = G.ahead[c];
-    if (j >= c0l) {  // an arrival of this step
-      const uint2 h = s_nhot[li][j - c0l];
-      const int2 cc = s_ncold[li][j - c0l];
-      hw = (v2u){h.x, h.y};
-      cw = (v2i){cc.x, cc.y};
-    }
-    if (j > 0 && j - 1 >= c0l) ahead = s_nhot[li][j - 1 - c0l].x;
-    const int x = xvf_x(hw.x), v = xvf_v(hw.x);
-    const uint32_t fl = xvf_fl(hw.x);
-    const int gap = j > 0 ? xvf_x(ahead) - x - 1 : llen - 1 - x + s_extra[li];
-    const int v1 = min(v + 1, cx.vmax);
-    const int v2 = min(v1, gap);
-    const uint32_t u = veh_draw(hw.y, (uint32_t)cx.t, 1u, cx.key0, cx.key1);
-    const int v3 = (v2 > 0 && (uint64_t)u < cx.slow_thr) ? v2 - 1 : v2;
-    const int nx = x + v3;
-    sumv += v3;
-    if (nx < llen) {
-      const uint32_t nw = pack_xvf(nx, v3, fl);
-      if (j >= c0l) {  // an arrival: its whole record
-        hot[G.sl[c]] = (v2u){nw, hw.y};
-        cold[G.sl[c]] = cw;
-      } else {
-        hot_w[2 * G.sl[c]] = nw;
-      }
-      const int lcnt = s_pre[li + 1] - s_pre[li];
-      if (j == 0) {
-        s_ends[li].x = (int)nw;
-        s_ends[li].y = cw.y;
-      } else if (j == 1) {
-        s_second[li] = make_int2((int)nw, cw.y);
-      }
-      if (j == lcnt - 1) s_ends[li].z = (int)nw;
-    } else {  // only a lead vehicle of the previous step passes the node
-      const int rp = cw.x;
-      exit_t[rp] = cx.t;
-      s_left[li] = 1;
-      if (fl & kFlLast) {
-        ++exits;
-      } else {
-        const uint32_t nfl = rinfo_flags((uint32_t)cw.y);
-        const int tg = s_tgt[li];
-        hb_out[tg] = (nfl & kFlLast) ? 0 : (int)route_info[rp + 2];
-        ha_out[tg] = (v4i){cx.t, (int)pack_xvf(nx - llen, v3, nfl),
-                           (int)hw.y, rp + 1};
-        ht_out[tg] = (cx.t << 1) | (nx == llen ? 1 : 0);
-        ++cross;
-      }
-    }
-  }
-}
-
-// ---------------------------------------------------------------------------
-// One kernel per step (see layout.h for when this is exact).  A wavefront
-// takes a tile, one lane per thread, and performs the whole step on it:
-//   1. merges the vehicle handed over to each lane in the previous step and
-//      lets the head of each link's parking queue enter the lowest lane
-//      whose cell 0 is empty (the arrivals join at the rear, in LDS);
-//   2. decides each lead vehicle near the node: trip end (extra = vmax), or
-//      the claim on its target lane that the previous step registered --
-//      the smallest (rank, lane) key wins -- and, for the winner, the rear
-//      of the target lane after that lane's own step-1 arrivals, recomputed
-//      from the target link's previous state by the same rule;
-//   3. moves every vehicle (second sub-step), rear first, 64 at a time;
-//   4. writes the lanes' state for the next step and registers the claims
-//      of the lanes' new lead vehicles for the next step.
-template <bool kBatched>
-__global__ __launch_bounds__(kWave) void k_step(
-    const DevScen* __restrict__ descs, int slot, const int4* __restrict__ work,
-    int step) {
-  __shared__ int s_pre[kMaxTileLanes + 1];
-  __shared__ int s_base[kMaxTileLanes], s_hp[kMaxTileLanes],
-      s_len[kMaxTileLanes], s_cnt0[kMaxTileLanes], s_tgt[kMaxTileLanes],
-      s_extra[kMaxTileLanes], s_left[kMaxTileLanes];
-  __shared__ int4 s_ends[kMaxTileLanes];    // new lead xvf/ninfo, rear xvf
-  __shared__ int2 s_second[kMaxTileLanes];  // the vehicle behind the lead
-  __shared__ uint2 s_nhot[kMaxTileLanes][2];  // arrivals of this step
-  __shared__ int2 s_ncold[kMaxTileLanes][2];
-  __shared__ int4 s_plans[kMaxPlans];
-  const long long c0 = wall_clock64();
-  const int4 w = work[blockIdx.x];
-  const DevScen& S = descs[kBatched ? w.x : slot];
-  const int t = S.t + step;
-  const int p = t & 1;
-  const long long Q = S.n_lanes;
-  const int vmax = S.vmax;
-  const uint32_t key0 = S.key0, key1 = S.key1;
-  const uint64_t slow_thr = S.slow_thr;
-  const GAS v4i* __restrict__ ls_cur = gpv<v4i>(S.lane_state + p * Q);
-  GAS v4i* __restrict__ ls_nxt = gpv<v4i>(S.lane_state + (p ^ 1) * Q);
-  const GAS v4i* __restrict__ ha_in = gpv<v4i>(S.hand_a + (p ^ 1) * Q);
-  const GAS int32_t* __restrict__ hb_in = gp(S.hand_b + (p ^ 1) * Q);
-  GAS v4i* __restrict__ ha_out = gpv<v4i>(S.hand_a + p * Q);
-  GAS int32_t* __restrict__ hb_out = gp(S.hand_b + p * Q);
-  GAS int32_t* __restrict__ cl_cur = gp(S.claim + p * Q);
-  GAS int32_t* __restrict__ cl_nxt = gp(S.claim + (p ^ 1) * Q);
-  const GAS int32_t* __restrict__ qn_cur = gp(S.qnext + p * Q);
-  GAS int32_t* __restrict__ qn_nxt = gp(S.qnext + (p ^ 1) * Q);
-  const GAS int32_t* __restrict__ ht_in = gp(S.hand_tag + (p ^ 1) * Q);
-  const GAS v2i* __restrict__ lane_bm = gpv<v2i>(S.lane_bm);
-  const GAS int32_t* __restrict__ lane_qend = gp(S.lane_qend);
-  GAS int32_t* __restrict__ ht_out = gp(S.hand_tag + p * Q);
-  GAS int32_t* __restrict__ lane_qhead = gp(S.lane_qhead);
-  GAS v4i* __restrict__ lane_qrec = gpv<v4i>(S.lane_qrec);
-  const GAS v4i* __restrict__ wait_rec = gpv<v4i>(S.wait_rec);
-  // hot and hot_w name the same records (loads / xvf stores): no restrict
-  GAS v2u* hot = gpv<v2u>(S.hot);
-  GAS uint32_t* hot_w = gpv<uint32_t>(S.hot);
-  GAS v2i* cold = gpv<v2i>(S.cold);
-  const GAS uint32_t* __restrict__ route_info = gp(S.route_info);
-  GAS int32_t* __restrict__ exit_t = gp(S.exit_t);
-  const int i = threadIdx.x;
-  const int nl = w.z;
-  const bool act = i < nl;
-  const int g = w.y + i;
-
-  // 1. what every lane needs from the previous step, in one round: its
-  // static word, its state, the tag of the last handoff into it and (lane
-  // 0) the departure time of its link's queue head
-  // (threads past the tile's lanes read its first lane and drop it, so
-  // that no load waits behind a branch)
-  const int gg = act ? g : w.y;
-  v2i bm = lane_bm[gg];
-  v4i st = ls_cur[gg];
-  int htag = ht_in[gg], qn = qn_cur[gg];
-  if (!act) {
-    bm = (v2i){0, 0};
-    st = (v4i){0, 0, 0, 0};
-    htag = kTagNone;
-    qn = INT32_MAX;
-  }
-  load_plans(S, s_plans);
-  const uint32_t meta = (uint32_t)bm.y;
-  const int len = act ? lmeta_len(meta) : 1;
-  const int k = lmeta_k(meta), lanes = lmeta_lanes(meta);
-  const int key = lmeta_rank(meta) * 8 + k;
-  const int head = hc_head(st.w);
-  const int cnt = act ? hc_cnt(st.w) : 0;
-  const uint32_t lead_w = (uint32_t)st.x;
-  // a vehicle handed over in the previous step joins at the rear (its
-  // record is read below); the tag says whether it landed on cell 0
-  bool arr = false;
-  if (act && (htag >> 1) == t - 1) {
-    if (cnt >= len) atomicOr(S.err, SIM_DEVERR_LANE_FULL);
-    else arr = true;
-  }
-  const int rear_x =
-      arr ? ((htag & 1) ? 0 : 1) : (cnt > 0 ? xvf_x((uint32_t)st.z) : 1);
-  const bool empty0 = act && rear_x != 0;
-  const unsigned long long free0 = __ballot(empty0);
-  const int l0 = i - k;  // this link's lane 0 in the tile
-  const int qn0 = __shfl(qn, l0);
-  int ins = 0;
-  if (empty0) {
-    const unsigned long long lm = (free0 >> l0) & ((1ull << lanes) - 1ull);
-    if (__builtin_ctzll(lm) == k && qn0 <= t) ins = 1;
-  }
-  const unsigned long long insm = __ballot(ins);
-  const bool link_ins =
-      act && k == 0 && ((insm >> i) & ((1ull << lanes) - 1ull)) != 0;
-  const int n_new = (arr ? 1 : 0) + ins;
-  // second round, only where something arrives: the handed-over record,
-  // and the head of the parking queue (read by lane 0, which also
-  // prefetches the next head for the next step)
-  v4i ha = {0, 0, 0, 0}, qrec = {0, 0, 0, 0}, nrec = {-1, 0, 0, 0};
-  int hb = 0, qh = 0, qend = 0;
-  if (arr) {
-    ha = ha_in[g];
-    hb = hb_in[g];
-  }
-  if (link_ins) {
-    qh = lane_qhead[g];
-    qrec = lane_qrec[g];
-    qend = lane_qend[g];
-  }
-
-  // 2. the lead vehicle at the node: target lane, its claim, and the
-  // arrivals of the target link's lanes (read by every candidate, used by
-  // the winner)
-  // (a red light holds it back: no claim, no trip end)
-  wave_lds_sync();  // the plans in LDS
-  const bool cand = act && cnt > 0 && len - 1 - xvf_x(lead_w) < vmax &&
-                    !sig_red(s_plans, meta, t);
-  const bool exits_here = cand && (xvf_fl(lead_w) & kFlLast);
-  int tgt = exits_here ? -2 : -1, tm = 0, tlanes = 1, tl0 = 0;
-  int claim = INT32_MAX, tqn = INT32_MAX;
-  int trear[4], tpend[4], tcnt[4];
-  if (cand && !exits_here) {
-    const uint32_t ni = (uint32_t)st.y;
-    tl0 = rinfo_lane0(ni);
-    tlanes = rinfo_lanes(ni);
-    tm = min(k, tlanes - 1);
-    tgt = tl0 + tm;
-    claim = cl_cur[tgt];
-    tqn = qn_cur[tl0];
-  }
-#pragma unroll
-  for (int m = 0; m < 4; ++m) {
-    trear[m] = 0;
-    tpend[m] = kTagNone;
-    tcnt[m] = 0;
-    if (tgt >= 0 && m < tlanes) {
-      const v4i ts = ls_cur[tl0 + m];
-      const v4i th = ha_in[tl0 + m];
-      trear[m] = (int)ts.z;
-      tcnt[m] = hc_cnt(ts.w);
-      tpend[m] = th.x == t - 1 ? th.y : kTagNone;
-    }
-  }
-  if (act) {
-    s_base[i] = bm.x;
-    s_hp[i] = hc_make(head, 0, 0);
-    s_len[i] = len;
-    s_cnt0[i] = cnt;
-    s_tgt[i] = tgt;
-    s_left[i] = 0;
-    s_ends[i] = make_int4(0, 0, 0, 0);
-  }
-  const int cntn = cnt + n_new;
-  int incl = cntn;
-#pragma unroll
-  for (int off = 1; off < kWave; off <<= 1) {
-    const int y = __shfl_up(incl, off);
-    if (i >= off) incl += y;
-  }
-  const int total = __builtin_amdgcn_readfirstlane(__shfl(incl, kWave - 1));
-  if (i < nl) s_pre[i] = incl - cntn;
-  if (i == 0) s_pre[nl] = total;
-  const unsigned long long cocc =
-      wave_sum((unsigned long long)(cntn > 0 ? len : 0));
-  wave_lds_sync();
-
-  // 3. the move, groups of kGroup x 64 vehicles from the rear: a group
-  // loads every record it needs before it rewrites any, so each vehicle
-  // reads the position of the one ahead before that one moves
-  unsigned long long sumv = 0, cross = 0, exits = 0;
-  const int nchunk = (total + kWave - 1) / kWave;
-  const StepCtx cx{t, vmax, key0, key1, slow_thr};
-  bool first = true;
-  // (one pass with no vehicle still decides the winners)
-  for (int gr = ((nchunk - 1) / kGroup) * kGroup; gr >= 0; gr -= kGroup) {
-    StepGroup G;
-    step_load(G, gr, i, total, nl, s_pre, s_len, s_base, s_hp, hot, hot_w,
-              cold);
-    if (first) {
-      first = false;
-      // the arrivals' records go to LDS; the inserting lane takes the queue
-      // head that lane 0 of its link read
-      const int qid = __shfl(qrec.x, l0), qdep = __shfl(qrec.y, l0),
-                qrp = __shfl(qrec.z, l0), qni = __shfl(qrec.w, l0);
-      if (arr) {
-        s_nhot[i][0] = make_uint2((uint32_t)ha.y, (uint32_t)ha.z);
-        s_ncold[i][0] = make_int2(ha.w, hb);
-      }
-      if (ins) {
-        s_nhot[i][arr ? 1 : 0] = make_uint2(
-            pack_xvf(0, 0, (uint32_t)qdep >> kDepartBits), (uint32_t)qid);
-        s_ncold[i][arr ? 1 : 0] = make_int2(qrp, qni);
-      }
-      if (link_ins && qh + 1 < qend) nrec = wait_rec[qh + 1];
-      // winners: extra cells past the link end (rule R7); the claim is
-      // cleared for the next use of this buffer
-      if (act) {
-        int extra = exits_here ? vmax : 0;
-        if (tgt >= 0 && claim == key) {
-          cl_cur[tgt] = INT32_MAX;
-          // the target link's step-1 arrivals, by the rule of part 1
-          int rx[4];
-          unsigned free_m = 0;
-#pragma unroll
-          for (int m = 0; m < 4; ++m) {
-            rx[m] = tpend[m] != kTagNone ? xvf_x((uint32_t)tpend[m])
-                    : tcnt[m] > 0         ? xvf_x((uint32_t)trear[m])
-                                          : vmax;
-            if (m < tlanes && rx[m] != 0) free_m |= 1u << m;
-          }
-          const bool tins =
-              tqn <= t && free_m != 0 && __builtin_ctz(free_m) == tm;
-          extra = tins ? 0 : min(vmax, rx[tm]);
-        }
-        s_extra[i] = extra;
-      }
-      wave_lds_sync();
-    }
-    step_run(G, cx, s_len, s_cnt0, s_pre, s_extra, s_tgt, s_nhot, s_ncold,
-             s_ends, s_second, s_left, hot, hot_w, cold, route_info, exit_t,
-             ha_out, hb_out, ht_out, sumv, cross, exits);
-  }
-  wave_lds_sync();
-
-  // 4. the lanes for the next step, and the claims of their new leads
-  if (act) {
-    int4 e = s_ends[i];
-    int h1 = head, c1 = cntn;
-    if (s_left[i]) {
-      h1 = wrapi(head + 1, len);
-      c1 = cntn - 1;
-      const int2 sec = s_second[i];
-      e.x = sec.x;  // the vehicle behind is the new lead
-      e.y = sec.y;
-    }
-    ls_nxt[g] = (v4i){e.x, e.y, e.z, hc_make(h1, 0, c1)};
-    if (c1 > 0 && len - 1 - xvf_x((uint32_t)e.x) < vmax &&
-        !(xvf_fl((uint32_t)e.x) & kFlLast) && !sig_red(s_plans, meta, t + 1)) {
-      const uint32_t ni = (uint32_t)e.y;
-      atomicMin((int*)&cl_nxt[rinfo_lane0(ni) + min(k, rinfo_lanes(ni) - 1)],
-                key);
-    }
-    if (k == 0) {
-      if (link_ins) {
-        lane_qhead[g] = qh + 1;
-        lane_qrec[g] = nrec;
-        qn_nxt[g] = qh + 1 < qend ? (nrec.y & ((1 << kDepartBits) - 1))
-                                  : INT32_MAX;
-      } else {
-        qn_nxt[g] = qn;
-      }
-    }
-  }
-  sumv = wave_sum(sumv);
-  cross = wave_sum(cross);
-  exits = wave_sum(exits);
-  const unsigned long long n_ins = wave_sum((unsigned long long)ins);
-  if (i == 0) {
-    GAS unsigned long long* ctr =
-        (GAS unsigned long long*)gp(S.tile_ctr + (long long)w.y * C_N);
-    atomicAdd((unsigned long long*)&ctr[C_UPDATES], (unsigned long long)total);
-    atomicAdd((unsigned long long*)&ctr[C_SUMV], sumv);
-    if (cross) atomicAdd((unsigned long long*)&ctr[C_CROSS], cross);
-    if (exits) atomicAdd((unsigned long long*)&ctr[C_EXITS], exits);
-    if (n_ins) atomicAdd((unsigned long long*)&ctr[C_INS], n_ins);
-    atomicAdd((unsigned long long*)&ctr[C_COCC], cocc);
-    atomicAdd((unsigned long long*)&ctr[C_CYCLES],
-              (unsigned long long)(wall_clock64() - c0));
-  }
-}
-
-__global__ void k_advance(DevScen* descs, const int* slots, int n, int k) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) descs[slots[i]].t += k;
-}
-
-// Ring mode: one workgroup holds a whole ring in LDS and runs every step.
-// Vehicles are kept in cyclic order; vehicle j follows vehicle j+1 (mod n).
-__global__ __launch_bounds__(kRingBlock) void k_ring(DevScen* descs,
-                                                     const int* slots,
-                                                     int n_steps) {
-  __shared__ int sx[2][kRingMax];
-  __shared__ unsigned char sv[2][kRingMax];
-  __shared__ int sid[kRingMax];
-  __shared__ unsigned long long s_sum;
-  DevScen& S = descs[slots[blockIdx.x]];
-  const int n = S.ring_n, L = S.ring_L, vmax = S.vmax;
-  const int t0 = S.t;
-  const int tid = threadIdx.x;
-  if (tid == 0) s_sum = 0;
-  for (int j = tid; j < n; j += kRingBlock) {
-    sx[0][j] = S.ring_x[j];
-    sv[0][j] = (unsigned char)S.ring_v[j];
-    sid[j] = S.ring_id[j];
-  }
-  __syncthreads();
-  int cur = 0;
-  unsigned long long sumv = 0;
-  for (int s = 0; s < n_steps; ++s) {
-    const uint32_t t = (uint32_t)(t0 + s);
-    for (int j = tid; j < n; j += kRingBlock) {
-      const int x = sx[cur][j];
-      int gap;
-      if (n == 1) {
-        gap = L - 1;
-      } else {
-        gap = sx[cur][j + 1 == n ? 0 : j + 1] - x - 1;
-        if (gap < 0) gap += L;
-      }
-      const int v1 = min((int)sv[cur][j] + 1, vmax);
-      const int v2 = min(v1, gap);
-      const uint32_t u = veh_draw((uint32_t)sid[j], t, 1u, S.key0, S.key1);
-      const int v3 = (v2 > 0 && (uint64_t)u < S.slow_thr) ? v2 - 1 : v2;
-      int nx = x + v3;
-      if (nx >= L) nx -= L;
-      sx[cur ^ 1][j] = nx;
-      sv[cur ^ 1][j] = (unsigned char)v3;
-      sumv += v3;
-    }
-    cur ^= 1;
-    __syncthreads();
-  }
-  for (int j = tid; j < n; j += kRingBlock) {
-    S.ring_x[j] = sx[cur][j];
-    S.ring_v[j] = sv[cur][j];
-  }
-  atomicAdd(&s_sum, sumv);
-  __syncthreads();
-  if (tid == 0) {
-    S.ring_ctr[C_UPDATES] += (long long)n * n_steps;
-    S.ring_ctr[C_SUMV] += (long long)s_sum;
-    S.ring_ctr[C_COCC] += n > 0 ? (long long)L * n_steps : 0;
-    S.t = t0 + n_steps;
-  }
-}
-
-// ---- stats and state export ----------------------------------------------
-
-namespace {
-
-__device__ __forceinline__ uint64_t mix64(uint64_t z) {
-  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-  return z ^ (z >> 31);
-}
-
-// hash of one vehicle's state (sum over vehicles = the state hash)
-__device__ __forceinline__ uint64_t veh_hash(int id, int st, int link, int lane,
-                                             int x, int v, int rptr) {
-  const uint64_t w = (uint64_t)st | ((uint64_t)(uint32_t)lane << 4) |
-                     ((uint64_t)(uint32_t)v << 8) |
-                     ((uint64_t)((uint32_t)x & 0xFFFFu) << 16) |
-                     ((uint64_t)(uint32_t)link << 32);
-  const uint64_t h = mix64(mix64((uint64_t)(uint32_t)id) ^ w);
-  return mix64(h ^ (uint64_t)(uint32_t)rptr);
-}
-
-constexpr int kWaiting = 0, kActive = 1, kArrived = 2;
-
-}  // namespace
-
-__global__ void k_stats(const DevScen* d, unsigned long long* out, int ring) {
-  const DevScen& S = *d;
-  unsigned long long h = 0, act = 0, wait = 0;
-  const long long stride = (long long)gridDim.x * blockDim.x;
-  const long long g0 = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (ring) {
-    for (long long j = g0; j < S.ring_n; j += stride)
-      h += veh_hash(S.ring_id[j], kActive, 0, 0, S.ring_x[j], S.ring_v[j], 0);
-    act = 0;
-    if (g0 == 0) {
-      act = (unsigned long long)S.ring_n;
-      for (int c = 0; c < C_N; ++c)
-        atomicAdd(&out[c], (unsigned long long)S.ring_ctr[c]);
-    }
-  } else {
-    // move-tile counters: one per lane at most (balanced tiles included)
-    const long long n1 = S.n_veh, n2 = n1 + S.n_lanes, n3 = n2 + S.n_lanes,
-                    n4 = n3 + S.n_lanes, n5 = n4 + S.n_ftiles;
-    for (long long g = g0; g < n5; g += stride) {
-      if (g < n1) {
-        h += veh_hash((int)g, kArrived, 0, 0, 0, 0, 0);
-      } else if (g < n2) {
-        // lane k == 0 of a link holds the link's parking queue
-        const int gid = (int)(g - n1);
-        const int4 info = S.lane_info[gid];
-        if (lmeta_k((uint32_t)info.y) == 0)
-          for (int q = S.lane_qhead[gid]; q < info.w; ++q) {
-            const int id = S.wait_rec[q].x;
-            h += veh_hash(id, kWaiting, 0, 0, 0, 0, 0) -
-                 veh_hash(id, kArrived, 0, 0, 0, 0, 0);
-            ++wait;
-          }
-      } else if (g < n3) {
-        const int gid = (int)(g - n2);
-        const int4 info = S.lane_info[gid];
-        // the current state: buffer t & 1 of a fused slot; the handoffs of
-        // the last step: buffer (t - 1) & 1
-        const long long cur = S.fused ? (long long)(S.t & 1) * S.n_lanes : 0;
-        const long long hpv =
-            S.fused ? (long long)((S.t - 1) & 1) * S.n_lanes : 0;
-        const int hc = S.lane_state[cur + gid].w;
-        const int link = info.z;
-        const int k = lmeta_k((uint32_t)info.y);
-        const int len = lmeta_len((uint32_t)info.y);
-        const int base = info.x;
-        for (int j = 0; j < hc_cnt(hc); ++j) {
-          const int slot = rec_slot(base, hc, len, j);
-          const uint2 hw = S.hot[slot];
-          const int id = (int)hw.y;
-          const int rptr = (int)(S.cold[slot].x - S.route_off[id]);
-          h += veh_hash(id, kActive, S.link_ext[link], k, xvf_x(hw.x),
-                        xvf_v(hw.x), rptr) -
-               veh_hash(id, kArrived, 0, 0, 0, 0, 0);
-        }
-        act += hc_cnt(hc);
-        // a vehicle handed over in the last step is on this lane already
-        const int4 ha = S.hand_a[hpv + gid];
-        if (ha.x == S.t - 1) {
-          const int id = ha.z;
-          h += veh_hash(id, kActive, S.link_ext[link], k, xvf_x((uint32_t)ha.y),
-                        xvf_v((uint32_t)ha.y), (int)(ha.w - S.route_off[id])) -
-               veh_hash(id, kArrived, 0, 0, 0, 0, 0);
-          ++act;
-        }
-      } else if (g < n4) {
-        const long long tile = g - n3;
-        for (int c = 0; c < C_N; ++c)
-          atomicAdd(&out[c], (unsigned long long)S.tile_ctr[tile * C_N + c]);
-      } else {
-        const long long tile = g - n4;
-        for (int c = 0; c < C_N; ++c)
-          atomicAdd(&out[c], (unsigned long long)S.ftile_ctr[tile * C_N + c]);
-      }
-    }
-  }
-  atomicAdd(&out[C_N], act);
-  atomicAdd(&out[C_N + 1], h);
-  atomicAdd(&out[C_N + 2], wait);
-}
-
-__global__ void k_export_fill(ExportBufs o, int n) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  o.status[i] = kArrived;
-  o.link[i] = -1;
-  o.lane[i] = 0;
-  o.x[i] = 0;
-  o.v[i] = 0;
-  o.rptr[i] = 0;
-}
-
-__global__ void k_export_set(const DevScen* d, ExportBufs o, int ring) {
-  const DevScen& S = *d;
-  const int g = blockIdx.x * blockDim.x + threadIdx.x;
-  if (ring) {
-    if (g >= S.ring_n) return;
-    const int id = S.ring_id[g];
-    o.status[id] = kActive;
-    o.link[id] = 0;
-    o.x[id] = S.ring_x[g];
-    o.v[id] = (int8_t)S.ring_v[g];
-    return;
-  }
-  if (g < S.n_lanes) {
-    const int4 info = S.lane_info[g];
-    if (lmeta_k((uint32_t)info.y) == 0)
-      for (int q = S.lane_qhead[g]; q < info.w; ++q)
-        o.status[S.wait_rec[q].x] = kWaiting;
-  } else if (g < 2 * S.n_lanes) {
-    const int gid = g - S.n_lanes;
-    const long long cur = S.fused ? (long long)(S.t & 1) * S.n_lanes : 0;
-    const long long hpv = S.fused ? (long long)((S.t - 1) & 1) * S.n_lanes : 0;
-    const int hc = S.lane_state[cur + gid].w;
-    const int4 info = S.lane_info[gid];
-    const int link = info.z;
-    const int k = lmeta_k((uint32_t)info.y);
-    const int len = lmeta_len((uint32_t)info.y);
-    const int base = info.x;
-    for (int j = 0; j < hc_cnt(hc); ++j) {
-      const int slot = rec_slot(base, hc, len, j);
-      const uint2 hw = S.hot[slot];
-      const int id = (int)hw.y;
-      o.status[id] = kActive;
-      o.link[id] = S.link_ext[link];
-      o.lane[id] = (int8_t)k;
-      o.x[id] = xvf_x(hw.x);
-      o.v[id] = (int8_t)xvf_v(hw.x);
-      o.rptr[id] = (int)(S.cold[slot].x - S.route_off[id]);
-    }
-    const int4 ha = S.hand_a[hpv + gid];
-    if (ha.x == S.t - 1) {  // handed over in the last step
-      const int id = ha.z;
-      o.status[id] = kActive;
-      o.link[id] = S.link_ext[link];
-      o.lane[id] = (int8_t)k;
-      o.x[id] = xvf_x((uint32_t)ha.y);
-      o.v[id] = (int8_t)xvf_v((uint32_t)ha.y);
-      o.rptr[id] = (int)(ha.w - S.route_off[id]);
-    }
-  }
-}
-
 // ---- launchers -------------------------------------------------------------
 
+// Each launcher first clears any error left by earlier runtime calls of this
+// thread, so that the status it returns is the launch's own.
 hipError_t launch_front(const DevScen* d_descs, int slot, const int4* d_work,
                         int n_work, int pieces, int step, int lc_words,
                         hipStream_t s) {
@@ -1531,24 +843,6 @@ hipError_t launch_back(const DevScen* d_descs, int slot, const int4* d_work,
   return hipGetLastError();
 }
 
-hipError_t launch_step(const DevScen* d_descs, int slot, const int4* d_work,
-                       int n_work, int step, hipStream_t s) {
-  if (n_work <= 0) return hipSuccess;
-  (void)hipGetLastError();
-  if (slot < 0)
-    hipLaunchKernelGGL(k_step<true>, dim3(n_work), dim3(kWave), 0, s, d_descs,
-                       0, d_work, step);
-  else
-    hipLaunchKernelGGL(k_step<false>, dim3(n_work), dim3(kWave), 0, s,
-                       d_descs, slot, d_work, step);
-  return hipGetLastError();
-}
-
-void* step_kernel(bool batched) {
-  return batched ? reinterpret_cast<void*>(&k_step<true>)
-                 : reinterpret_cast<void*>(&k_step<false>);
-}
-
 void* front_kernel(bool batched) {
   return batched ? reinterpret_cast<void*>(&k_front<true>)
                  : reinterpret_cast<void*>(&k_front<false>);
@@ -1556,48 +850,6 @@ void* front_kernel(bool batched) {
 void* back_kernel(bool batched) {
   return batched ? reinterpret_cast<void*>(&k_back<true>)
                  : reinterpret_cast<void*>(&k_back<false>);
-}
-void* advance_kernel() { return reinterpret_cast<void*>(&k_advance); }
-
-// Each launcher first clears any error left by earlier runtime calls of this
-// thread, so that the status it returns is the launch's own.
-hipError_t launch_advance(DevScen* d_descs, const int* d_slots, int n, int k,
-                          hipStream_t s) {
-  if (n <= 0) return hipSuccess;
-  (void)hipGetLastError();
-  hipLaunchKernelGGL(k_advance, dim3((n + 63) / 64), dim3(64), 0, s, d_descs,
-                     d_slots, n, k);
-  return hipGetLastError();
-}
-
-hipError_t launch_ring(DevScen* d_descs, const int* d_slots, int n,
-                       int n_steps, hipStream_t s) {
-  if (n <= 0) return hipSuccess;
-  (void)hipGetLastError();
-  hipLaunchKernelGGL(k_ring, dim3(n), dim3(kRingBlock), 0, s, d_descs,
-                     d_slots, n_steps);
-  return hipGetLastError();
-}
-
-hipError_t launch_stats(const DevScen* d_desc, unsigned long long* d_out,
-                        int ring, hipStream_t s) {
-  (void)hipGetLastError();
-  hipLaunchKernelGGL(k_stats, dim3(1024), dim3(256), 0, s, d_desc, d_out,
-                     ring);
-  return hipGetLastError();
-}
-
-hipError_t launch_export(const DevScen* d_desc, ExportBufs out, int n_veh,
-                         int n_links, int n_lanes, int ring, hipStream_t s) {
-  (void)hipGetLastError();
-  if (n_veh > 0)
-    hipLaunchKernelGGL(k_export_fill, dim3((n_veh + 255) / 256), dim3(256), 0,
-                       s, out, n_veh);
-  const int n = ring ? n_veh : 2 * n_lanes;
-  if (n > 0)
-    hipLaunchKernelGGL(k_export_set, dim3((n + 255) / 256), dim3(256), 0, s,
-                       d_desc, out, ring);
-  return hipGetLastError();
 }
 
 }  // namespace tr
