@@ -120,6 +120,14 @@ def family_of(kinds) -> str:
 # (x 2.0 and x 1.0).  Valid only for the kernel sources with this digest
 # (of the kernel's family).
 MEASURED_TRAFFIC = {
+    "5b2a5ddbe759e68e": {
+        # k_step<false>: FETCH 2589.3 KiB x 2.0 + WRITE 2577.9 KiB x 1.0
+        "portland": {"steps": 3600, "bytes_per_launch": 7756.5 * 1024},
+        # k_step<true>, 64 scenarios (tiles of 64 lanes / 8,192 cells, the
+        # tuner's choice under the profiler): FETCH 43611.2 x 2.0 + WRITE
+        # 43109.7 x 1.0
+        "batched": {"steps": 3600, "bytes_per_launch": 130332.1 * 1024},
+    },
 }
 
 
