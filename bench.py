@@ -97,13 +97,22 @@ FAMILY = {"step": "step", "front": "front_back", "back": "front_back",
           "ring": "ring"}
 
 
+def _code_only(text: str) -> str:
+    """The source without comments, trailing blanks and empty lines, so that
+    a comment edit does not change what counts as the measured code."""
+    import re
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    lines = (re.sub(r"//.*$", "", ln).rstrip() for ln in text.split("\n"))
+    return "\n".join(ln for ln in lines if ln)
+
+
 def kernel_digest(family: str = "step") -> str:
     import hashlib
     h = hashlib.sha256()
     for f in KERNEL_SOURCES[family]:
         with open(os.path.join(ROOT, "paper_cs_0105004_amd", "csrc", f),
-                  "rb") as fh:
-            h.update(fh.read())
+                  encoding="utf-8") as fh:
+            h.update(_code_only(fh.read()).encode())
     return h.hexdigest()[:16]
 
 
@@ -120,7 +129,7 @@ def family_of(kinds) -> str:
 # (x 2.0 and x 1.0).  Valid only for the kernel sources with this digest
 # (of the kernel's family).
 MEASURED_TRAFFIC = {
-    "5b2a5ddbe759e68e": {
+    "5f5f880d34fcdc43": {
         # k_step<false>: FETCH 2589.3 KiB x 2.0 + WRITE 2577.9 KiB x 1.0
         "portland": {"steps": 3600, "bytes_per_launch": 7756.5 * 1024},
         # k_step<true>, 64 scenarios (tiles of 64 lanes / 8,192 cells, the

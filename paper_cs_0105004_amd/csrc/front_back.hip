@@ -151,7 +151,7 @@ struct LcTile {
   uint32_t* rw;      // rear record's xvf word after the sub-step
 };
 
-// Lane, record slot and xvf word of vehicle f of the tile's lattice
+// Lane and record slot of vehicle f of the tile's lattice
 // (f < V; lanes in order, each lane lead first)
 __device__ __forceinline__ void lc_locate(const LcTile& T, int nl, int f,
                                           int& ln, int& slot) {
