@@ -178,7 +178,8 @@ def cpu_baseline(scen, budget_s: float):
             "cores": 1, "kind": "oracle",
             "sample": f"steps 0..{steps - 1} of the same workload "
                       f"({st['veh_updates']} vehicle-updates, {dt:.1f} s, "
-                      f"single thread)"}
+                      f"single thread)",
+            "host": host_info()}
 
 
 def roofline_from(kt, stats_list, region_ms=None, workload=None, steps=None):
@@ -219,6 +220,94 @@ def roofline_from(kt, stats_list, region_ms=None, workload=None, steps=None):
             "launches": {k: kt[k][0] for k in kinds}}
 
 
+def host_info() -> dict:
+    """CPU model and core counts of the host the oracle runs on."""
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"cpu_model": model, "nproc": os.cpu_count(),
+            "usable_cores": usable}
+
+
+def oracle_all_cores(scens, budget_s: float, max_workers: int = 16):
+    """The host's aggregate oracle rate over independent scenarios: one
+    thread per scenario (the oracle is C called through ctypes, which
+    releases the GIL while it steps), each from its start, for about
+    budget_s seconds.  At most max_workers threads (the host's share for
+    one GPU)."""
+    import threading
+    import oracle
+    n = max(1, min(max_workers, host_info()["usable_cores"] or 1, len(scens)))
+    sims = [oracle.OracleSim(sc) for sc in scens[:n]]  # created one by one
+    done = [0] * n
+    t0 = time.perf_counter()
+    stop = t0 + budget_s
+
+    def run(k):
+        sc = scens[k]
+        while time.perf_counter() < stop and done[k] < sc.T:
+            m = min(25, sc.T - done[k])
+            sims[k].step(m)
+            done[k] += m
+
+    threads = [threading.Thread(target=run, args=(k,)) for k in range(n)]
+    for th in threads:
+        th.start()
+    for th in threads:
+        th.join()
+    dt = time.perf_counter() - t0
+    upd = sum(o.stats()["veh_updates"] for o in sims)
+    for o in sims:
+        o.close()
+    return {"value": upd / dt, "unit": "vehicle-updates/s", "cores": n,
+            "kind": "oracle",
+            "sample": f"{n} scenario(s) of the same workload, one thread "
+                      f"each, from t = 0, {sum(done)} scenario-steps "
+                      f"({upd} vehicle-updates, {dt:.1f} s)",
+            "host": host_info()}
+
+
+def copy_bandwidth(nbytes: int = 1 << 30, reps: int = 5) -> float:
+    """GB/s of a plain device-to-device copy of nbytes (bytes read plus
+    bytes written), the best of reps: the reachable HBM rate, beside the
+    published peak."""
+    import torch
+    a = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1)
+    b.copy_(a)
+    best = float("inf")
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        torch.cuda.synchronize()
+        best = min(best, e0.elapsed_time(e1))
+    del a, b
+    return 2.0 * nbytes / (best * 1e-3) / 1e9
+
+
+def with_copy_reference(roof):
+    """Adds the measured copy bandwidth and the fraction of it achieved."""
+    if roof is not None:
+        cg = copy_bandwidth()
+        roof["copy_gbs"] = cg
+        roof["frac_of_copy"] = roof["achieved"] / cg
+    return roof
+
+
 def oracle_sample(scens, budget_s: float):
     """The oracle over the given scenarios one after another (each from its
     start) until about budget_s seconds of CPU time are spent."""
@@ -242,7 +331,8 @@ def oracle_sample(scens, budget_s: float):
             "kind": "oracle",
             "sample": f"{used} scenario(s) of the same workload from t = 0, "
                       f"{steps} scenario-steps ({upd} vehicle-updates, "
-                      f"{dt:.1f} s, single thread)"}
+                      f"{dt:.1f} s, single thread)",
+            "host": host_info()}
 
 
 def bench_batched(args):
@@ -293,8 +383,9 @@ def bench_batched(args):
     ctx.profile(False)
     for k in slots:
         assert ctx.stats(k)["hash"] == stats[k]["hash"], "replay diverged"
-    roof = roofline_from(kt, stats, region_ms, workload="batched",
-                         steps=args.steps)
+    roof = with_copy_reference(roofline_from(kt, stats, region_ms,
+                                             workload="batched",
+                                             steps=args.steps))
     ctx.close()
     log("bench: plain loop")
     plain = Context(max_slots=1, graph_steps=-1)
@@ -330,6 +421,8 @@ def bench_batched(args):
     if not args.no_cpu_baseline:
         log(f"bench: oracle sample ({args.cpu_seconds:.0f} s budget)")
         out["cpu_baseline"] = oracle_sample(scens, args.cpu_seconds)
+        log(f"bench: oracle on all host cores ({args.cpu_seconds:.0f} s)")
+        out["cpu_all_cores"] = oracle_all_cores(scens, args.cpu_seconds)
     print(json.dumps(out), flush=True)
     return 0
 
@@ -373,7 +466,7 @@ def bench_serve(args):
     res2 = srv.run(short, realtime=True)
     kt = srv.ctx.kernel_times()
     srv.close()
-    roof = roofline_from(kt, [r.stats for r in res2])
+    roof = with_copy_reference(roofline_from(kt, [r.stats for r in res2]))
     cfg = {"workload": "serving_poisson", "rate_per_s": 4.0,
            "window_s": args.window, "requests": len(trace), "pool_sets": 32,
            "links_range": [1000, 50000], "vehicles_per_link": 10,
@@ -392,6 +485,9 @@ def bench_serve(args):
         log(f"bench: oracle sample ({args.cpu_seconds:.0f} s budget)")
         out["cpu_baseline"] = oracle_sample([q.scen for q in trace[:3]],
                                             args.cpu_seconds)
+        log(f"bench: oracle on all host cores ({args.cpu_seconds:.0f} s)")
+        out["cpu_all_cores"] = oracle_all_cores([q.scen for q in trace[:16]],
+                                                args.cpu_seconds)
     print(json.dumps(out), flush=True)
     return 0
 
@@ -510,6 +606,7 @@ def main():
                 "kernel_sources_digest": digest,
                 "kernel_ms": {k: kt[k][1] for k in kinds},
                 "launches": {k: kt[k][0] for k in kinds}}
+    with_copy_reference(roof)
     srt = sorted(runs)
 
     def pct(q):
