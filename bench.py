@@ -274,7 +274,7 @@ def oracle_all_cores(scens, budget_s: float, max_workers: int = 16):
             "sample": f"{n} scenario(s) of the same workload, one thread "
                       f"each, from t = 0, {sum(done)} scenario-steps "
                       f"({upd} vehicle-updates, {dt:.1f} s)",
-            "host": host_info()}
+            "vehicle_updates": upd, "host": host_info()}
 
 
 def copy_bandwidth(nbytes: int = 1 << 30, reps: int = 5) -> float:

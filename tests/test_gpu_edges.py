@@ -118,3 +118,34 @@ def test_no_vehicles(mode):
     g = ctx.state(0)
     assert all(len(g[k]) == 0 for k in ("status", "x", "exit_t"))
     ctx.close()
+
+
+def test_batched_lane_change_slots_with_different_lattices():
+    # three lane-changing scenarios stepped in the same launches: the launch
+    # reserves LDS for the largest lattice (4-lane links of ~15k cells), each
+    # slot's tiles use their own part of it
+    def lengths(rng, m):
+        return rng.integers(14000, 16001, size=m)
+    flags = S.FLAG_LANE_CHANGE | S.FLAG_TURN_LANES
+    scens = [
+        S.grid_scenario(3, 3, 16, 300, T=200, depart_max=40, seed=19,
+                        len_sampler=lengths, lanes_range=(4, 4), flags=flags),
+        S.portland_like(scale=0.01, T=200, depart_max=100, seed=51,
+                        flags=flags),
+        S.grid_scenario(4, 5, 40, 3000, T=200, depart_max=0, seed=52,
+                        lanes_range=(2, 4), flags=flags),
+    ]
+    from paper_cs_0105004_amd.sim import Context
+    ctx = Context(max_slots=len(scens))
+    for k, sc in enumerate(scens):
+        ctx.load(k, sc)
+    ctx.step([0, 1, 2], 150)
+    ctx.step([0, 2], 30)  # uneven progress
+    steps = [180, 150, 180]
+    for k, sc in enumerate(scens):
+        o = oracle.OracleSim(sc)
+        o.step(steps[k])
+        assert_same_stats(ctx.stats(k), o.stats(), f"slot {k}")
+        assert_same_state(ctx.state(k), o.state(), f"slot {k}")
+        assert o.stats()["lane_changes"] > 0
+    ctx.close()
