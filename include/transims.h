@@ -121,7 +121,11 @@ typedef struct {
   const int8_t* conn_hi;
   const double* node_xy;   /* optional [2*n_nodes]; used only for tiling     */
   const float* link_cost;  /* optional [n_links] tiling weights (e.g. costs
-                              measured by sim_link_costs on an earlier run)  */
+                              measured by sim_link_costs on an earlier run):
+                              they weight the ORB cuts, and a tile also
+                              stops at the mean weight of the tiles the
+                              lane and cell caps alone would make (Section
+                              "Adaptive Load Balancing")                    */
   /* optional fixed-time signals at the downstream end of links (Section
      "Microsimulation driving logic": while the light is red a virtual
      vehicle of speed zero stands at the end of the lane).  signal_plan[l]

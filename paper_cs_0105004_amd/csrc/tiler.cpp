@@ -84,6 +84,32 @@ std::vector<int2> pack_tiles(const std::vector<int32_t>& lanes,
   return tiles;
 }
 
+std::vector<int2> pack_tiles(const std::vector<int32_t>& lanes,
+                             const std::vector<int32_t>& len,
+                             const std::vector<double>& weight, int tile_lanes,
+                             int64_t max_cells, double max_weight) {
+  std::vector<int2> tiles;
+  int32_t first = 0, cur = 0;
+  int64_t cells = 0;
+  double wsum = 0.0;
+  for (size_t l = 0; l < lanes.size(); ++l) {
+    const int64_t c = (int64_t)lanes[l] * len[l];
+    if (cur > 0 && (cur + lanes[l] > tile_lanes || cells + c > max_cells ||
+                    wsum + weight[l] > max_weight)) {
+      tiles.push_back(make_int2(first, cur));
+      first += cur;
+      cur = 0;
+      cells = 0;
+      wsum = 0.0;
+    }
+    cur += lanes[l];
+    cells += c;
+    wsum += weight[l];
+  }
+  if (cur > 0) tiles.push_back(make_int2(first, cur));
+  return tiles;
+}
+
 std::vector<int2> xcd_interleave(const std::vector<int2>& tiles, int domains) {
   const int64_t n = (int64_t)tiles.size();
   std::vector<int64_t> start(domains + 1);

@@ -34,6 +34,14 @@ std::vector<int2> pack_tiles(const std::vector<int32_t>& lanes,
                              const std::vector<int32_t>& len, int tile_lanes,
                              int64_t max_cells);
 
+// The same with a weight per link (the measured cost of adaptive load
+// balancing): a tile also takes no link that would bring its weight past
+// max_weight, unless the tile is still empty.
+std::vector<int2> pack_tiles(const std::vector<int32_t>& lanes,
+                             const std::vector<int32_t>& len,
+                             const std::vector<double>& weight, int tile_lanes,
+                             int64_t max_cells, double max_weight);
+
 // Deals a list of tiles to `domains` XCDs: XCD x gets the x-th contiguous
 // chunk, and position p of the result runs on XCD p mod domains.
 std::vector<int2> xcd_interleave(const std::vector<int2>& tiles, int domains);

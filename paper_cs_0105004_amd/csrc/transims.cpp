@@ -424,6 +424,19 @@ extern "C" sim_status sim_load_network(sim_ctx* c, int32_t slot,
   S.ftiles = (S.fused || lc_slot)
                  ? pack_tiles(S.lanes, S.len, tile_lanes, c->cfg.tile_cells)
                  : pack_tiles(S.lanes, tile_lanes);
+  if (net->link_cost && !S.ring) {
+    // adaptive load balancing: with measured per-link costs a tile also
+    // stops at the mean measured cost of the tiles above, so that the
+    // links that cost most get tiles of their own
+    double total = 0.0;
+    for (int32_t i = 0; i < L; ++i) total += S.weight[i];
+    const double cap = total / (double)std::max<size_t>(S.ftiles.size(), 1);
+    if (cap > 0.0)
+      S.ftiles = pack_tiles(S.lanes, S.len, S.weight, tile_lanes,
+                            (S.fused || lc_slot) ? (int64_t)c->cfg.tile_cells
+                                                 : INT64_MAX,
+                            cap);
+  }
   S.n_ftiles = (int32_t)S.ftiles.size();
   S.lc_words = 0;
   if (lc_slot) {
