@@ -7,7 +7,8 @@ HIP kernels of libtransims, called via its C ABI.  The default workload is
 the Portland-sized synthetic network (77 x 78 grid thinned to 20,024
 directed links of 1-3 lanes, 200,000 routed vehicles departing uniformly in
 the first 1,800 s, vmax 5, p = 0.2), run for its full 3,600-step horizon
-from t = 0 with all inputs resident in HBM.
+from t = 0 with all inputs resident in HBM, 6 times from a fresh load; the
+rate is the median run's.
 
 Prints one JSON line with vehicle-updates/s, the simulated-to-real-time
 ratio, the roofline position of the dominant kernel (timed with HIP events)
@@ -362,17 +363,31 @@ def bench_batched(args):
     for k, sc in enumerate(scens):
         ctx.load(k, sc)
     torch.cuda.synchronize()
-    log(f"bench: timing {args.steps} batched steps")
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    t0 = time.perf_counter()
-    ev0.record(ctx.stream)
-    ctx.step(slots, args.steps)
-    ev1.record(ctx.stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    region_ms = ev0.elapsed_time(ev1)
+    log(f"bench: timing {args.steps} batched steps, "
+        f"{1 + max(args.reps, 0)} runs")
+
+    def timed_run():
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        ev0.record(ctx.stream)
+        ctx.step(slots, args.steps)
+        ev1.record(ctx.stream)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, ev0.elapsed_time(ev1)
+
+    # 1 + reps runs from a fresh load of every slot; the median run's rate
+    runs = [timed_run()]
     stats = [ctx.stats(k) for k in slots]
+    for _ in range(max(args.reps, 0)):
+        for k, sc in enumerate(scens):
+            ctx.load(k, sc)
+        torch.cuda.synchronize()
+        runs.append(timed_run())
+        for k in slots:
+            assert ctx.stats(k)["hash"] == stats[k]["hash"], "repeat diverged"
+    wall, region_ms = sorted(runs)[len(runs) // 2]
+    walls = sorted(r[0] for r in runs)
     upd = sum(st["veh_updates"] for st in stats)
     # kernel times of the same run, replayed with events
     for k, sc in enumerate(scens):
@@ -415,6 +430,11 @@ def bench_batched(args):
            "dtype": "int32", "data": "synthetic", "config": cfg,
            "sim_real_time_ratio_per_scenario": args.steps / wall,
            "vehicle_updates": upd, "wall_s": wall,
+           "run_latency_ms": {
+               "p50": walls[len(walls) // 2] * 1e3,
+               "p99": walls[min(len(walls) - 1,
+                                int(round(0.99 * (len(walls) - 1))))] * 1e3,
+               "runs": len(walls)},
            "plain_loop": {"value": pupd / pwall, "wall_s": pwall},
            "speedup_vs_plain_loop": (upd / wall) / (pupd / pwall),
            "autotune": tune["trials"], "roofline": roof}
@@ -539,30 +559,32 @@ def main():
     ctx.unload(1)
     ctx.load(0, scen)
     torch.cuda.synchronize()
-    log(f"bench: timing {args.steps} steps")
-    # HIP events on the library's stream bracket the timed region
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    t0 = time.perf_counter()
-    ev0.record(ctx.stream)
-    ctx.step(0, args.steps)
-    ev1.record(ctx.stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    region_ms = ev0.elapsed_time(ev1)
-    st = ctx.stats(0)
-    value = st["veh_updates"] / wall
+    log(f"bench: timing {args.steps} steps, {1 + max(args.reps, 0)} runs")
 
-    # run latency: the same K-step run from a fresh load, several times
-    runs = [wall]
+    def timed_run():
+        """The K steps from a fresh load: wall time and the time between HIP
+        events on the library's stream around the same region."""
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        ev0.record(ctx.stream)
+        ctx.step(0, args.steps)
+        ev1.record(ctx.stream)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, ev0.elapsed_time(ev1)
+
+    # the same K-step run from a fresh load, 1 + reps times; the reported
+    # rate is the median run's (the runs also give the latency percentiles)
+    runs = [timed_run()]
+    st = ctx.stats(0)
     for _ in range(max(args.reps, 0)):
         ctx.load(0, scen)
         torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        ctx.step(0, args.steps)
-        torch.cuda.synchronize()
-        runs.append(time.perf_counter() - t1)
+        runs.append(timed_run())
         assert ctx.stats(0)["hash"] == st["hash"], "repeat run diverged"
+    wall, region_ms = sorted(runs)[len(runs) // 2]
+    runs = [r[0] for r in runs]
+    value = st["veh_updates"] / wall
 
     # kernel timing pass: the same K steps again, inside HIP graphs with an
     # event between every two kernels on the library's stream
