@@ -180,7 +180,18 @@ def cpu_baseline(scen, budget_s: float):
             "sample": f"steps 0..{steps - 1} of the same workload "
                       f"({st['veh_updates']} vehicle-updates, {dt:.1f} s, "
                       f"single thread)",
-            "host": host_info()}
+            "host": host_info()}, st
+
+
+def oracle_check(ctx, scen, ost) -> dict:
+    """The GPU from a fresh load to the step the oracle reached: every
+    counter and the state hash must be equal."""
+    ctx.load(0, scen)
+    ctx.step(0, int(ost["t"]))
+    gst = ctx.stats(0)
+    diff = sorted(k for k in ost if gst.get(k) != ost[k])
+    return {"steps": int(ost["t"]), "state_hash": f"{ost['hash']:016x}",
+            "equal": not diff, "differing": diff}
 
 
 def roofline_from(kt, stats_list, region_ms=None, workload=None, steps=None):
@@ -315,6 +326,7 @@ def oracle_sample(scens, budget_s: float):
     import oracle
     t0 = time.perf_counter()
     upd, steps, used = 0, 0, 0
+    finals = []
     for sc in scens:
         o = oracle.OracleSim(sc)
         done = 0
@@ -322,7 +334,8 @@ def oracle_sample(scens, budget_s: float):
             k = min(25, sc.T - done)
             o.step(k)
             done += k
-        upd += o.stats()["veh_updates"]
+        finals.append(o.stats())
+        upd += finals[-1]["veh_updates"]
         steps += done
         used += 1
         if time.perf_counter() - t0 >= budget_s:
@@ -333,7 +346,7 @@ def oracle_sample(scens, budget_s: float):
             "sample": f"{used} scenario(s) of the same workload from t = 0, "
                       f"{steps} scenario-steps ({upd} vehicle-updates, "
                       f"{dt:.1f} s, single thread)",
-            "host": host_info()}
+            "host": host_info()}, finals
 
 
 def bench_batched(args):
@@ -440,7 +453,23 @@ def bench_batched(args):
            "autotune": tune["trials"], "roofline": roof}
     if not args.no_cpu_baseline:
         log(f"bench: oracle sample ({args.cpu_seconds:.0f} s budget)")
-        out["cpu_baseline"] = oracle_sample(scens, args.cpu_seconds)
+        out["cpu_baseline"], finals = oracle_sample(scens, args.cpu_seconds)
+        # the sampled scenarios again on the GPU, each in its own slot, to
+        # the step the oracle reached
+        log("bench: GPU against the oracle on the sampled scenarios")
+        ctx = Context(max_slots=len(finals), tile_lanes=tune["tile_lanes"],
+                      graph_steps=tune["graph_steps"],
+                      tile_cells=tune["tile_cells"])
+        checks = []
+        for k, ost in enumerate(finals):
+            ctx.load(k, scens[k])
+            ctx.step(k, int(ost["t"]))
+            gst = ctx.stats(k)
+            checks.append({"scenario": k, "steps": int(ost["t"]),
+                           "equal": all(gst.get(c) == ost[c] for c in ost)})
+        ctx.close()
+        out["oracle_check"] = {"equal": all(c["equal"] for c in checks),
+                               "scenarios": checks}
         log(f"bench: oracle on all host cores ({args.cpu_seconds:.0f} s)")
         out["cpu_all_cores"] = oracle_all_cores(scens, args.cpu_seconds)
     print(json.dumps(out), flush=True)
@@ -503,8 +532,8 @@ def bench_serve(args):
            "roofline": roof}
     if not args.no_cpu_baseline:
         log(f"bench: oracle sample ({args.cpu_seconds:.0f} s budget)")
-        out["cpu_baseline"] = oracle_sample([q.scen for q in trace[:3]],
-                                            args.cpu_seconds)
+        out["cpu_baseline"], _ = oracle_sample([q.scen for q in trace[:3]],
+                                               args.cpu_seconds)
         log(f"bench: oracle on all host cores ({args.cpu_seconds:.0f} s)")
         out["cpu_all_cores"] = oracle_all_cores([q.scen for q in trace[:16]],
                                                 args.cpu_seconds)
@@ -648,10 +677,12 @@ def main():
                    "e_tile": tiling["e_tile"]},
         "roofline": roof,
     }
-    ctx.close()
     if not args.no_cpu_baseline:
         log(f"bench: oracle sample ({args.cpu_seconds:.0f} s budget)")
-        out["cpu_baseline"] = cpu_baseline(scen, args.cpu_seconds)
+        out["cpu_baseline"], ost = cpu_baseline(scen, args.cpu_seconds)
+        log(f"bench: GPU against the oracle at step {ost['t']}")
+        out["oracle_check"] = oracle_check(ctx, scen, ost)
+    ctx.close()
     print(json.dumps(out), flush=True)
     return 0
 
