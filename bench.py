@@ -363,8 +363,9 @@ def bench_batched(args):
     n = len(scens)
     slots = list(range(n))
     log("bench: autotuning")
-    tune = autotune(scens, warm_steps=min(600, args.steps), trial_steps=128,
-                    reps=2, log=log)
+    # trials at the demand peak (mid-horizon), where the step costs most
+    tune = autotune(scens, warm_steps=min(1800, args.steps // 2),
+                    trial_steps=128, reps=2, log=log)
     ctx = Context(max_slots=n, tile_lanes=tune["tile_lanes"],
                   back_pieces=tune["back_pieces"],
                   graph_steps=tune["graph_steps"],

@@ -17,7 +17,7 @@ import time
 from typing import Dict, List, Sequence
 
 TILE_LANES = (8, 16, 32, 64)
-TILE_CELLS = (1024, 2048, 4096, 8192, 16384)
+TILE_CELLS = (1024, 2048, 4096, 6144, 8192, 12288, 16384)
 BACK_PIECES = (1, 2, 4, 8)
 GRAPH_STEPS = (32, 64, 128)
 
