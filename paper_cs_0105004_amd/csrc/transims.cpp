@@ -30,6 +30,9 @@ constexpr int kDefaultGraphSteps = 64;
 // one-kernel steps: a tile also stops at this many cells, so that no
 // wavefront is left with a much longer queue of vehicles than the rest
 constexpr int kDefaultTileCells = 2048;
+// tiles of scenarios with lane changes (their cell cap also bounds the
+// lane-change lattice in LDS)
+constexpr int kDefaultLcTileCells = 4096;
 
 struct Slot {
   bool net = false, veh = false, ring = false;
@@ -300,7 +303,6 @@ extern "C" sim_status sim_create(const sim_config* cfg, sim_ctx** out) {
   c->cfg = *cfg;
   if (c->cfg.back_pieces == 0) c->cfg.back_pieces = kDefaultBackPieces;
   if (c->cfg.graph_steps == 0) c->cfg.graph_steps = kDefaultGraphSteps;
-  if (c->cfg.tile_cells == 0) c->cfg.tile_cells = kDefaultTileCells;
   c->stream = reinterpret_cast<hipStream_t>(cfg->stream);
   c->slots.resize(cfg->max_slots);
   if (hipGetDevice(&c->device) != hipSuccess ||
@@ -421,8 +423,11 @@ extern "C" sim_status sim_load_network(sim_ctx* c, int32_t slot,
   const int tile_lanes = c->cfg.tile_lanes != 0 ? c->cfg.tile_lanes
                          : lc_slot              ? kDefaultLcTileLanes
                                                 : kDefaultTileLanes;
+  const int tile_cells = c->cfg.tile_cells != 0 ? c->cfg.tile_cells
+                         : lc_slot              ? kDefaultLcTileCells
+                                                : kDefaultTileCells;
   S.ftiles = (S.fused || lc_slot)
-                 ? pack_tiles(S.lanes, S.len, tile_lanes, c->cfg.tile_cells)
+                 ? pack_tiles(S.lanes, S.len, tile_lanes, tile_cells)
                  : pack_tiles(S.lanes, tile_lanes);
   if (net->link_cost && !S.ring) {
     // adaptive load balancing: with measured per-link costs a tile also
@@ -433,7 +438,7 @@ extern "C" sim_status sim_load_network(sim_ctx* c, int32_t slot,
     const double cap = total / (double)std::max<size_t>(S.ftiles.size(), 1);
     if (cap > 0.0)
       S.ftiles = pack_tiles(S.lanes, S.len, S.weight, tile_lanes,
-                            (S.fused || lc_slot) ? (int64_t)c->cfg.tile_cells
+                            (S.fused || lc_slot) ? (int64_t)tile_cells
                                                  : INT64_MAX,
                             cap);
   }
