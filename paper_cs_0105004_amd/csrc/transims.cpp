@@ -46,6 +46,8 @@ struct Slot {
   std::vector<int8_t> conn_lo, conn_hi;
   std::vector<int2> tiles, ftiles;  // move sub-step / lane-change sub-step
   std::vector<double> weight;  // internal order
+  std::vector<double> ftile_w;  // summed link weight of each tile
+  bool measured = false;        // weights are measured costs (link_cost)
   uint8_t* ws = nullptr;
   uint64_t ws_bytes = 0, ws_net = 0;
   DevScen d{};
@@ -443,6 +445,14 @@ extern "C" sim_status sim_load_network(sim_ctx* c, int32_t slot,
                             cap);
   }
   S.n_ftiles = (int32_t)S.ftiles.size();
+  S.measured = net->link_cost != nullptr && !S.ring;
+  S.ftile_w.assign(S.ftiles.size(), 0.0);
+  {
+    int32_t l = 0;
+    for (size_t t = 0; t < S.ftiles.size(); ++t)
+      for (; l < L && S.lane0[l] < S.ftiles[t].x + S.ftiles[t].y; ++l)
+        S.ftile_w[t] += S.weight[l];
+  }
   S.lc_words = 0;
   if (lc_slot) {
     int32_t l = 0;
@@ -835,7 +845,22 @@ sim_status build_work(sim_ctx* c, const std::vector<int32_t>& net,
       for (int32_t t = 0; t < S.n_ftiles; ++t) all.push_back(make_int2(sl, t));
       if (pass == 1) lc = std::max(lc, S.lc_words);
     }
-    const std::vector<int2> dealt = xcd_interleave(all, 8);
+    std::vector<int2> dealt = xcd_interleave(all, 8);
+    // with measured costs, each XCD starts its costliest tiles first (its
+    // set of tiles, and so its L2 region, stays the same), which shortens
+    // the tail of the launch
+    bool measured = !all.empty();
+    for (const int2& a : all) measured = measured && c->slots[a.x].measured;
+    if (measured) {
+      for (size_t x = 0; x < 8; ++x) {
+        std::vector<int2> mine;
+        for (size_t k = x; k < dealt.size(); k += 8) mine.push_back(dealt[k]);
+        std::stable_sort(mine.begin(), mine.end(), [&](int2 a, int2 b) {
+          return c->slots[a.x].ftile_w[a.y] > c->slots[b.x].ftile_w[b.y];
+        });
+        for (size_t k = x, j = 0; k < dealt.size(); k += 8, ++j) dealt[k] = mine[j];
+      }
+    }
     for (size_t k = 0; k < dealt.size(); ++k) {
       const int2 tl = c->slots[dealt[k].x].ftiles[dealt[k].y];
       work.push_back(make_int4(dealt[k].x, tl.x, tl.y, dealt[k].y));
