@@ -8,7 +8,10 @@ the Portland-sized synthetic network (77 x 78 grid thinned to 20,024
 directed links of 1-3 lanes, 200,000 routed vehicles departing uniformly in
 the first 1,800 s, vmax 5, p = 0.2), run for its full 3,600-step horizon
 from t = 0 with all inputs resident in HBM, 6 times from a fresh load; the
-rate is the median run's.
+rate is the median run's.  As in the paper's series of runs, the tiling of
+the timed runs is weighted by the link costs an earlier, untimed run of the
+same horizon measured (adaptive load balancing); the same runs without that
+feedback are reported beside them.
 
 Prints one JSON line with vehicle-updates/s, the simulated-to-real-time
 ratio, the roofline position of the dominant kernel (timed with HIP events)
@@ -183,10 +186,10 @@ def cpu_baseline(scen, budget_s: float):
             "host": host_info()}, st
 
 
-def oracle_check(ctx, scen, ost) -> dict:
+def oracle_check(ctx, scen, ost, link_cost=None) -> dict:
     """The GPU from a fresh load to the step the oracle reached: every
     counter and the state hash must be equal."""
-    ctx.load(0, scen)
+    ctx.load(0, scen, link_cost=link_cost)
     ctx.step(0, int(ost["t"]))
     gst = ctx.stats(0)
     diff = sorted(k for k in ost if gst.get(k) != ost[k])
@@ -374,11 +377,20 @@ def bench_batched(args):
         ctx.load(k, sc)
     ctx.step(slots, args.warmup)
     torch.cuda.synchronize()
-    for k, sc in enumerate(scens):
-        ctx.load(k, sc)
-    torch.cuda.synchronize()
-    log(f"bench: timing {args.steps} batched steps, "
-        f"{1 + max(args.reps, 0)} runs")
+    # adaptive load balancing: an untimed run of the whole horizon measures
+    # every slot's link costs; the timed runs are tiled and ordered by them
+    costs = [None] * n
+    if not args.no_feedback:
+        log(f"bench: cost-measuring run of {args.steps} batched steps")
+        for k, sc in enumerate(scens):
+            ctx.load(k, sc)
+        ctx.step(slots, args.steps)
+        costs = [ctx.link_costs(k) for k in slots]
+
+    def load_all(cs):
+        for k, sc in enumerate(scens):
+            ctx.load(k, sc, link_cost=cs[k])
+        torch.cuda.synchronize()
 
     def timed_run():
         ev0 = torch.cuda.Event(enable_timing=True)
@@ -390,22 +402,34 @@ def bench_batched(args):
         torch.cuda.synchronize()
         return time.perf_counter() - t0, ev0.elapsed_time(ev1)
 
-    # 1 + reps runs from a fresh load of every slot; the median run's rate
-    runs = [timed_run()]
-    stats = [ctx.stats(k) for k in slots]
-    for _ in range(max(args.reps, 0)):
-        for k, sc in enumerate(scens):
-            ctx.load(k, sc)
-        torch.cuda.synchronize()
-        runs.append(timed_run())
-        for k in slots:
-            assert ctx.stats(k)["hash"] == stats[k]["hash"], "repeat diverged"
-    wall, region_ms = sorted(runs)[len(runs) // 2]
-    walls = sorted(r[0] for r in runs)
+    def timed_runs(cs):
+        """1 + reps runs from a fresh load of every slot: the median run's
+        (wall, event time), the sorted walls, and every slot's counters."""
+        out, st0 = [], None
+        for _ in range(1 + max(args.reps, 0)):
+            load_all(cs)
+            out.append(timed_run())
+            st1 = [ctx.stats(k) for k in slots]
+            assert st0 is None or all(a["hash"] == b["hash"]
+                                      for a, b in zip(st0, st1)), "diverged"
+            st0 = st1
+        return sorted(out)[len(out) // 2], sorted(r[0] for r in out), st0
+
+    log(f"bench: timing {args.steps} batched steps, "
+        f"{1 + max(args.reps, 0)} runs")
+    (wall, region_ms), walls, stats = timed_runs(costs)
     upd = sum(st["veh_updates"] for st in stats)
+    cold = None
+    if not args.no_feedback:
+        log("bench: the same runs without cost feedback")
+        (cwall, _), cwalls, cstats = timed_runs([None] * n)
+        assert all(a["hash"] == b["hash"] for a, b in zip(stats, cstats))
+        cold = {"value": upd / cwall,
+                "ms_per_step": cwall * 1e3 / max(args.steps, 1),
+                "run_latency_ms": {"p50": cwalls[len(cwalls) // 2] * 1e3,
+                                   "runs": len(cwalls)}}
     # kernel times of the same run, replayed with events
-    for k, sc in enumerate(scens):
-        ctx.load(k, sc)
+    load_all(costs)
     ctx.profile(True)
     ctx.step(slots, args.steps)
     kt = ctx.kernel_times()
@@ -449,6 +473,10 @@ def bench_batched(args):
                "p99": walls[min(len(walls) - 1,
                                 int(round(0.99 * (len(walls) - 1))))] * 1e3,
                "runs": len(walls)},
+           "load_balancing": ("link costs measured by an untimed run of the "
+                              "whole horizon (adaptive load balancing)"
+                              if cold is not None else "none (static tiling)"),
+           "without_feedback": cold,
            "plain_loop": {"value": pupd / pwall, "wall_s": pwall},
            "speedup_vs_plain_loop": (upd / wall) / (pupd / pwall),
            "autotune": tune["trials"], "roofline": roof}
@@ -552,6 +580,8 @@ def main():
     ap.add_argument("--tile-cells", type=int, default=0)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-feedback", action="store_true",
+                    help="time the cold tiling only (no cost-measuring run)")
     ap.add_argument("--reps", type=int, default=5,
                     help="further runs of K steps for the run-latency "
                          "percentiles")
@@ -587,9 +617,17 @@ def main():
     ctx.step(1, args.warmup)
     ctx.stats(1)
     ctx.unload(1)
-    ctx.load(0, scen)
-    torch.cuda.synchronize()
-    log(f"bench: timing {args.steps} steps, {1 + max(args.reps, 0)} runs")
+    # adaptive load balancing, the paper's feedback between runs: an untimed
+    # run of the whole horizon measures every link's cost, and the timed
+    # runs are tiled and ordered with those costs (--no-feedback: without)
+    costs = None
+    if not args.no_feedback and args.workload != "ring":
+        log(f"bench: cost-measuring run of {args.steps} steps")
+        ctx.load(1, scen)
+        ctx.step(1, args.steps)
+        ctx.stats(1)
+        costs = ctx.link_costs(1)
+        ctx.unload(1)
 
     def timed_run():
         """The K steps from a fresh load: wall time and the time between HIP
@@ -603,22 +641,35 @@ def main():
         torch.cuda.synchronize()
         return time.perf_counter() - t0, ev0.elapsed_time(ev1)
 
-    # the same K-step run from a fresh load, 1 + reps times; the reported
-    # rate is the median run's (the runs also give the latency percentiles)
-    runs = [timed_run()]
-    st = ctx.stats(0)
-    for _ in range(max(args.reps, 0)):
-        ctx.load(0, scen)
-        torch.cuda.synchronize()
-        runs.append(timed_run())
-        assert ctx.stats(0)["hash"] == st["hash"], "repeat run diverged"
-    wall, region_ms = sorted(runs)[len(runs) // 2]
-    runs = [r[0] for r in runs]
+    def timed_runs(link_cost):
+        """The same K-step run from a fresh load, 1 + reps times: the median
+        run's (wall, event time), all walls, and the final counters."""
+        out, st0 = [], None
+        for _ in range(1 + max(args.reps, 0)):
+            ctx.load(0, scen, link_cost=link_cost)
+            torch.cuda.synchronize()
+            out.append(timed_run())
+            st1 = ctx.stats(0)
+            assert st0 is None or st1["hash"] == st0["hash"], "repeat diverged"
+            st0 = st1
+        return sorted(out)[len(out) // 2], [r[0] for r in out], st0
+
+    log(f"bench: timing {args.steps} steps, {1 + max(args.reps, 0)} runs")
+    (wall, region_ms), runs, st = timed_runs(costs)
     value = st["veh_updates"] / wall
+    cold = None
+    if costs is not None:
+        log("bench: the same runs without cost feedback")
+        (cwall, _), cruns, cst = timed_runs(None)
+        assert cst["hash"] == st["hash"], "feedback changed the result"
+        cold = {"value": cst["veh_updates"] / cwall,
+                "ms_per_step": cwall * 1e3 / max(args.steps, 1),
+                "run_latency_ms": {"p50": sorted(cruns)[len(cruns) // 2] * 1e3,
+                                   "runs": len(cruns)}}
 
     # kernel timing pass: the same K steps again, inside HIP graphs with an
     # event between every two kernels on the library's stream
-    ctx.load(0, scen)
+    ctx.load(0, scen, link_cost=costs)
     ctx.profile(True)
     ctx.step(0, args.steps)
     kt = ctx.kernel_times()
@@ -674,6 +725,10 @@ def main():
         "bit_exact_state_hash": f"{st['hash']:016x}",
         "run_latency_ms": {"p50": pct(0.5), "p99": pct(0.99),
                            "runs": len(runs)},
+        "load_balancing": ("link costs measured by an untimed run of the "
+                           "whole horizon (adaptive load balancing)"
+                           if costs is not None else "none (static tiling)"),
+        "without_feedback": cold,
         "tiling": {"tiles": tiling["n_tiles"], "e_dmn": tiling["e_dmn"],
                    "e_tile": tiling["e_tile"]},
         "roofline": roof,
@@ -682,7 +737,7 @@ def main():
         log(f"bench: oracle sample ({args.cpu_seconds:.0f} s budget)")
         out["cpu_baseline"], ost = cpu_baseline(scen, args.cpu_seconds)
         log(f"bench: GPU against the oracle at step {ost['t']}")
-        out["oracle_check"] = oracle_check(ctx, scen, ost)
+        out["oracle_check"] = oracle_check(ctx, scen, ost, costs)
     ctx.close()
     print(json.dumps(out), flush=True)
     return 0

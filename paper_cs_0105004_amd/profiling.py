@@ -3,6 +3,7 @@
     python -m paper_cs_0105004_amd.profiling stats  <run_kernel_stats.csv | run_results.db>
     python -m paper_cs_0105004_amd.profiling pmc    <run_counter_collection.csv | run_results.db> [LAST]
     python -m paper_cs_0105004_amd.profiling copy   <run_counter_collection.csv | run_results.db> BYTES
+    python -m paper_cs_0105004_amd.profiling last   <run_kernel_trace.csv> N
 
 `stats` prints calls / average / total duration per kernel from a
 `--kernel-trace --stats` run; `pmc` prints, per kernel, the dispatch count and
@@ -10,8 +11,11 @@ the mean of every collected counter per dispatch (FETCH_SIZE and WRITE_SIZE
 are in KiB), over the LAST dispatches of each kernel if given; `copy` prints
 the bytes one plain copy of BYTES bytes reads and writes according to those
 counters, i.e. the calibration factor that turns the counters of the step
-kernels into HBM bytes.  Each reads rocprofv3's CSV output or its SQLite
-database (`run_results.db`, the default output format).
+kernels into HBM bytes; `last` prints, per kernel, the mean duration of its
+last N dispatches in a `--kernel-trace` run (one pass of a bench that runs
+several configurations).  `stats`, `pmc` and `copy` read rocprofv3's CSV
+output or its SQLite database (`run_results.db`, the default output
+format); `last` reads the CSV kernel trace.
 """
 from __future__ import annotations
 
@@ -78,6 +82,23 @@ def counters(path: str, last: int = 0) -> dict:
     return out
 
 
+def last_durations(path: str, n: int) -> dict:
+    """{kernel: (dispatches used, mean ns)} over the last n dispatches of
+    each kernel, in dispatch order."""
+    rows = defaultdict(list)
+    with open(path, newline="") as f:
+        for row in csv.DictReader(f):
+            rows[short_name(row["Kernel_Name"])].append(
+                (int(row["Dispatch_Id"]),
+                 int(row["End_Timestamp"]) - int(row["Start_Timestamp"])))
+    out = {}
+    for k, v in rows.items():
+        v.sort()
+        v = v[-n:]
+        out[k] = (len(v), sum(d for _, d in v) / max(len(v), 1))
+    return out
+
+
 def main(argv) -> int:
     if len(argv) < 2:
         print(__doc__)
@@ -96,6 +117,12 @@ def main(argv) -> int:
         for k, cs in sorted(counters(path, last).items()):
             for c, (n, m) in sorted(cs.items()):
                 print(f"{k:36s} {c:14s} dispatches {n:7d} mean {m:14.1f}")
+    elif mode == "last":
+        n = int(argv[2])
+        print(f"{'kernel':36s} {'last':>8s} {'avg_us':>9s}")
+        for k, (m, avg) in sorted(last_durations(path, n).items(),
+                                  key=lambda kv: -kv[1][1] * kv[1][0]):
+            print(f"{k:36s} {m:8d} {avg / 1e3:9.3f}")
     elif mode == "copy":
         nbytes = float(argv[2])
         for k, cs in sorted(counters(path).items()):
