@@ -134,12 +134,12 @@ def family_of(kinds) -> str:
 # (of the kernel's family).
 MEASURED_TRAFFIC = {
     "5f5f880d34fcdc43": {
-        # k_step<false>: FETCH 2589.3 KiB x 2.0 + WRITE 2577.9 KiB x 1.0
-        "portland": {"steps": 3600, "bytes_per_launch": 7756.5 * 1024},
-        # k_step<true>, 64 scenarios (tiles of 64 lanes / 8,192 cells, the
-        # tuner's choice under the profiler): FETCH 43611.2 x 2.0 + WRITE
-        # 43109.7 x 1.0
-        "batched": {"steps": 3600, "bytes_per_launch": 130332.1 * 1024},
+        # k_step<false>, tiles weighted by measured link costs: FETCH
+        # 2632.1 KiB x 2.0 + WRITE 2628.5 KiB x 1.0
+        "portland": {"steps": 3600, "bytes_per_launch": 7892.7 * 1024},
+        # k_step<true>, 64 scenarios, 64-lane / 8,192-cell tiles weighted by
+        # measured link costs: FETCH 45043.7 x 2.0 + WRITE 43810.5 x 1.0
+        "batched": {"steps": 3600, "bytes_per_launch": 133897.9 * 1024},
     },
 }
 
@@ -365,10 +365,17 @@ def bench_batched(args):
     scens = S.batched_scenarios(T=args.steps)
     n = len(scens)
     slots = list(range(n))
-    log("bench: autotuning")
-    # trials at the demand peak (mid-horizon), where the step costs most
-    tune = autotune(scens, warm_steps=min(1800, args.steps // 2),
-                    trial_steps=128, reps=2, log=log)
+    if args.tile_lanes and args.tile_cells:
+        # a fixed configuration (e.g. for counter runs, where the profiler
+        # distorts the tuner's timings)
+        tune = {"tile_lanes": args.tile_lanes, "tile_cells": args.tile_cells,
+                "back_pieces": 1, "graph_steps": args.graph_steps or 64,
+                "trials": "skipped (fixed configuration)"}
+    else:
+        log("bench: autotuning")
+        # trials at the demand peak (mid-horizon), where the step costs most
+        tune = autotune(scens, warm_steps=min(1800, args.steps // 2),
+                        trial_steps=128, reps=2, log=log)
     ctx = Context(max_slots=n, tile_lanes=tune["tile_lanes"],
                   back_pieces=tune["back_pieces"],
                   graph_steps=tune["graph_steps"],
@@ -578,6 +585,9 @@ def main():
     ap.add_argument("--workload", default="portland")
     ap.add_argument("--tile-lanes", type=int, default=0)
     ap.add_argument("--tile-cells", type=int, default=0)
+    ap.add_argument("--graph-steps", type=int, default=0,
+                    help="batched: steps per graph with --tile-lanes and "
+                         "--tile-cells (which skip the autotuner)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-feedback", action="store_true",
