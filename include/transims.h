@@ -126,7 +126,8 @@ typedef struct {
                               they weight the ORB cuts, and a tile also
                               stops at the mean weight of the tiles the
                               lane and cell caps alone would make (Section
-                              "Adaptive Load Balancing")                    */
+                              "Adaptive Load Balancing"); each finite and
+                              >= 0, else SIM_E_INVAL                        */
   /* optional fixed-time signals at the downstream end of links (Section
      "Microsimulation driving logic": while the light is red a virtual
      vehicle of speed zero stands at the end of the lane).  signal_plan[l]

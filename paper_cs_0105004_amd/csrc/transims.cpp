@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -213,6 +214,8 @@ sim_status check_network(sim_ctx* c, const sim_params* p, const sim_network* n) 
       return fail(c, SIM_E_INVAL, "link %d: lanes must be 1..4", l);
     if (n->len[l] < p->vmax + 1 || n->len[l] > 32767)
       return fail(c, SIM_E_INVAL, "link %d: length must be vmax+1..32767", l);
+    if (n->link_cost && !(std::isfinite(n->link_cost[l]) && n->link_cost[l] >= 0.0f))
+      return fail(c, SIM_E_INVAL, "link %d: link_cost must be finite and >= 0", l);
     if (n->from[l] < 0 || n->from[l] >= n->n_nodes || n->to[l] < 0 ||
         n->to[l] >= n->n_nodes)
       return fail(c, SIM_E_INVAL, "link %d: node out of range", l);
@@ -378,7 +381,7 @@ extern "C" sim_status sim_load_network(sim_ctx* c, int32_t slot,
   // ---- tiling: ORB order of links, then whole links packed into tiles
   std::vector<double> w(L);
   for (int32_t l = 0; l < L; ++l)
-    w[l] = net->link_cost ? std::max(0.0f, net->link_cost[l])
+    w[l] = net->link_cost ? (double)net->link_cost[l]
                           : (double)net->len[l] * net->lanes[l];
   std::vector<int32_t> order(L);
   std::iota(order.begin(), order.end(), 0);

@@ -176,3 +176,33 @@ def test_link_cost_feedback_retiles_without_changing_results():
     assert ctx.stats(1)["hash"] == ctx.stats(0)["hash"]
     assert_same_state(ctx.state(1), st0, "re-tiled run")
     ctx.close()
+
+
+def test_link_cost_feedback_with_lane_changes_and_batches():
+    # measured costs also weight and order the tiles of the two-kernel step
+    # and of a batch (each slot its own costs); results do not change
+    import numpy as np
+    from paper_cs_0105004_amd.sim import Context, SimError
+    flags = S.FLAG_LANE_CHANGE | S.FLAG_TURN_LANES
+    scens = [S.portland_like(scale=0.03, T=300, depart_max=150, seed=61,
+                             flags=flags),
+             S.portland_like(scale=0.04, T=300, depart_max=150, seed=62),
+             S.portland_like(scale=0.02, T=300, depart_max=150, seed=63)]
+    ctx = Context(max_slots=len(scens))
+    for k, sc in enumerate(scens):
+        ctx.load(k, sc)
+    ctx.step([0, 1, 2], 300)
+    base = [ctx.stats(k) for k in range(3)]
+    costs = [ctx.link_costs(k) for k in range(3)]
+    for k, sc in enumerate(scens):
+        ctx.load(k, sc, link_cost=costs[k])
+    ctx.step([0, 1, 2], 300)
+    for k in range(3):
+        assert_same_stats(ctx.stats(k), base[k], f"fed-back slot {k}")
+    # costs must be finite and non-negative
+    for bad in (np.nan, -1.0, np.inf):
+        c = costs[1].copy()
+        c[3] = bad
+        with pytest.raises(SimError):
+            ctx.load(1, scens[1], link_cost=c)
+    ctx.close()
