@@ -8,10 +8,10 @@ the Portland-sized synthetic network (77 x 78 grid thinned to 20,024
 directed links of 1-3 lanes, 200,000 routed vehicles departing uniformly in
 the first 1,800 s, vmax 5, p = 0.2), run for its full 3,600-step horizon
 from t = 0 with all inputs resident in HBM, 6 times from a fresh load; the
-rate is the median run's.  As in the paper's series of runs, the tiling of
-the timed runs is weighted by the link costs an earlier, untimed run of the
-same horizon measured (adaptive load balancing); the same runs without that
-feedback are reported beside them.
+rate is the median run's.  Tiles are ordered by the load the vehicles'
+routes plan.  As in the paper's series of runs, the same runs are also timed
+with the tiling weighted by the link costs an earlier, untimed run measured
+(adaptive load balancing) and reported beside them.
 
 Prints one JSON line with vehicle-updates/s, the simulated-to-real-time
 ratio, the roofline position of the dominant kernel (timed with HIP events)
@@ -133,20 +133,16 @@ def family_of(kinds) -> str:
 # (x 2.0 and x 1.0).  Valid only for the kernel sources with this digest
 # (of the kernel's family).
 MEASURED_TRAFFIC = {
-    "5f5f880d34fcdc43": {
-        # k_step<false>, tiles weighted by measured link costs: FETCH
-        # 2632.1 KiB x 2.0 + WRITE 2628.5 KiB x 1.0
-        "portland": {"steps": 3600, "bytes_per_launch": 7892.7 * 1024},
-        # k_step<true>, 64 scenarios, 64-lane / 8,192-cell tiles weighted by
-        # measured link costs: FETCH 45043.7 x 2.0 + WRITE 43810.5 x 1.0
-        "batched": {"steps": 3600, "bytes_per_launch": 133897.9 * 1024},
-    },
 }
 
 
-def measured_traffic(family: str, workload: str, steps: int):
+def measured_traffic(family: str, workload: str, steps: int,
+                     tiles=(0, 0)):
+    """The measured bytes per launch for this kernel family, workload,
+    horizon and (tile_lanes, tile_cells) (0: the library default), if the
+    counters were taken on exactly that."""
     tr = MEASURED_TRAFFIC.get(kernel_digest(family), {}).get(workload)
-    if tr is None or tr["steps"] != steps:
+    if tr is None or tr["steps"] != steps or tuple(tr["tiles"]) != tuple(tiles):
         return None
     return tr["bytes_per_launch"]
 
@@ -197,7 +193,8 @@ def oracle_check(ctx, scen, ost, link_cost=None) -> dict:
             "equal": not diff, "differing": diff}
 
 
-def roofline_from(kt, stats_list, region_ms=None, workload=None, steps=None):
+def roofline_from(kt, stats_list, region_ms=None, workload=None, steps=None,
+                  tiles=(0, 0)):
     """Roofline object of the dominant step kernel from per-kernel times and
     the summed counters of the scenarios it processed.  With one step kernel
     and the event time of the timed region, the launch duration is that
@@ -225,7 +222,7 @@ def roofline_from(kt, stats_list, region_ms=None, workload=None, steps=None):
     fam = family_of(kinds)
     return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-            "traffic": (measured_traffic(fam, workload, steps)
+            "traffic": (measured_traffic(fam, workload, steps, tiles)
                         if workload else None),
             "kernel": name, "avg_launch_us": avg_ms * 1e3,
             "timing": timing,
@@ -385,7 +382,7 @@ def bench_batched(args):
     ctx.step(slots, args.warmup)
     torch.cuda.synchronize()
     # adaptive load balancing: an untimed run of the whole horizon measures
-    # every slot's link costs; the timed runs are tiled and ordered by them
+    # every slot's link costs; a second set of timed runs is tiled with them
     costs = [None] * n
     if not args.no_feedback:
         log(f"bench: cost-measuring run of {args.steps} batched steps")
@@ -424,28 +421,28 @@ def bench_batched(args):
 
     log(f"bench: timing {args.steps} batched steps, "
         f"{1 + max(args.reps, 0)} runs")
-    (wall, region_ms), walls, stats = timed_runs(costs)
+    (wall, region_ms), walls, stats = timed_runs([None] * n)
     upd = sum(st["veh_updates"] for st in stats)
-    cold = None
+    fed = None
     if not args.no_feedback:
-        log("bench: the same runs without cost feedback")
-        (cwall, _), cwalls, cstats = timed_runs([None] * n)
-        assert all(a["hash"] == b["hash"] for a, b in zip(stats, cstats))
-        cold = {"value": upd / cwall,
-                "ms_per_step": cwall * 1e3 / max(args.steps, 1),
-                "run_latency_ms": {"p50": cwalls[len(cwalls) // 2] * 1e3,
-                                   "runs": len(cwalls)}}
+        log("bench: the same runs with cost feedback")
+        (fwall, _), fwalls, fstats = timed_runs(costs)
+        assert all(a["hash"] == b["hash"] for a, b in zip(stats, fstats))
+        fed = {"value": upd / fwall,
+               "ms_per_step": fwall * 1e3 / max(args.steps, 1),
+               "run_latency_ms": {"p50": fwalls[len(fwalls) // 2] * 1e3,
+                                  "runs": len(fwalls)}}
     # kernel times of the same run, replayed with events
-    load_all(costs)
+    load_all([None] * n)
     ctx.profile(True)
     ctx.step(slots, args.steps)
     kt = ctx.kernel_times()
     ctx.profile(False)
     for k in slots:
         assert ctx.stats(k)["hash"] == stats[k]["hash"], "replay diverged"
-    roof = with_copy_reference(roofline_from(kt, stats, region_ms,
-                                             workload="batched",
-                                             steps=args.steps))
+    roof = with_copy_reference(roofline_from(
+        kt, stats, region_ms, workload="batched", steps=args.steps,
+        tiles=(tune["tile_lanes"], tune["tile_cells"])))
     ctx.close()
     log("bench: plain loop")
     plain = Context(max_slots=1, graph_steps=-1)
@@ -480,10 +477,8 @@ def bench_batched(args):
                "p99": walls[min(len(walls) - 1,
                                 int(round(0.99 * (len(walls) - 1))))] * 1e3,
                "runs": len(walls)},
-           "load_balancing": ("link costs measured by an untimed run of the "
-                              "whole horizon (adaptive load balancing)"
-                              if cold is not None else "none (static tiling)"),
-           "without_feedback": cold,
+           "load_balancing": "tiles ordered by the load the routes plan",
+           "with_feedback": fed,
            "plain_loop": {"value": pupd / pwall, "wall_s": pwall},
            "speedup_vs_plain_loop": (upd / wall) / (pupd / pwall),
            "autotune": tune["trials"], "roofline": roof}
@@ -591,7 +586,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-feedback", action="store_true",
-                    help="time the cold tiling only (no cost-measuring run)")
+                    help="skip the cost-measuring run and the runs tiled "
+                         "with its costs")
     ap.add_argument("--reps", type=int, default=5,
                     help="further runs of K steps for the run-latency "
                          "percentiles")
@@ -628,8 +624,9 @@ def main():
     ctx.stats(1)
     ctx.unload(1)
     # adaptive load balancing, the paper's feedback between runs: an untimed
-    # run of the whole horizon measures every link's cost, and the timed
-    # runs are tiled and ordered with those costs (--no-feedback: without)
+    # run of the whole horizon measures every link's cost, and a second set
+    # of timed runs is tiled with those costs (reported beside the default
+    # runs; --no-feedback: skip it)
     costs = None
     if not args.no_feedback and args.workload != "ring":
         log(f"bench: cost-measuring run of {args.steps} steps")
@@ -665,21 +662,21 @@ def main():
         return sorted(out)[len(out) // 2], [r[0] for r in out], st0
 
     log(f"bench: timing {args.steps} steps, {1 + max(args.reps, 0)} runs")
-    (wall, region_ms), runs, st = timed_runs(costs)
+    (wall, region_ms), runs, st = timed_runs(None)
     value = st["veh_updates"] / wall
-    cold = None
+    fed = None
     if costs is not None:
-        log("bench: the same runs without cost feedback")
-        (cwall, _), cruns, cst = timed_runs(None)
-        assert cst["hash"] == st["hash"], "feedback changed the result"
-        cold = {"value": cst["veh_updates"] / cwall,
-                "ms_per_step": cwall * 1e3 / max(args.steps, 1),
-                "run_latency_ms": {"p50": sorted(cruns)[len(cruns) // 2] * 1e3,
-                                   "runs": len(cruns)}}
+        log("bench: the same runs with cost feedback")
+        (fwall, _), fruns, fst = timed_runs(costs)
+        assert fst["hash"] == st["hash"], "feedback changed the result"
+        fed = {"value": fst["veh_updates"] / fwall,
+               "ms_per_step": fwall * 1e3 / max(args.steps, 1),
+               "run_latency_ms": {"p50": sorted(fruns)[len(fruns) // 2] * 1e3,
+                                  "runs": len(fruns)}}
 
     # kernel timing pass: the same K steps again, inside HIP graphs with an
     # event between every two kernels on the library's stream
-    ctx.load(0, scen, link_cost=costs)
+    ctx.load(0, scen)
     ctx.profile(True)
     ctx.step(0, args.steps)
     kt = ctx.kernel_times()
@@ -706,7 +703,8 @@ def main():
         achieved = bytes_launch / (avg_ms * 1e-3) / 1e9
         fam = family_of(kinds)
         digest = kernel_digest(fam)
-        traffic = measured_traffic(fam, args.workload, args.steps)
+        traffic = measured_traffic(fam, args.workload, args.steps,
+                                   (args.tile_lanes, args.tile_cells))
         roof = {"bound": "hbm", "achieved": achieved,
                 "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
@@ -735,10 +733,8 @@ def main():
         "bit_exact_state_hash": f"{st['hash']:016x}",
         "run_latency_ms": {"p50": pct(0.5), "p99": pct(0.99),
                            "runs": len(runs)},
-        "load_balancing": ("link costs measured by an untimed run of the "
-                           "whole horizon (adaptive load balancing)"
-                           if costs is not None else "none (static tiling)"),
-        "without_feedback": cold,
+        "load_balancing": "tiles ordered by the load the routes plan",
+        "with_feedback": fed,
         "tiling": {"tiles": tiling["n_tiles"], "e_dmn": tiling["e_dmn"],
                    "e_tile": tiling["e_tile"]},
         "roofline": roof,
@@ -747,7 +743,7 @@ def main():
         log(f"bench: oracle sample ({args.cpu_seconds:.0f} s budget)")
         out["cpu_baseline"], ost = cpu_baseline(scen, args.cpu_seconds)
         log(f"bench: GPU against the oracle at step {ost['t']}")
-        out["oracle_check"] = oracle_check(ctx, scen, ost, costs)
+        out["oracle_check"] = oracle_check(ctx, scen, ost)
     ctx.close()
     print(json.dumps(out), flush=True)
     return 0
