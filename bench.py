@@ -148,6 +148,9 @@ MEASURED_TRAFFIC = {
             # 43676.7 x 1.0
             {"steps": 3600, "tiles": (64, 12288),
              "bytes_per_launch": 134769.3 * 1024},
+            # 16,384-cell tiles: FETCH 45544.7 x 2.0 + WRITE 43681.3 x 1.0
+            {"steps": 3600, "tiles": (64, 16384),
+             "bytes_per_launch": 134770.7 * 1024},
         ],
     },
 }
