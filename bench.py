@@ -609,8 +609,8 @@ def main():
                     help="skip the cost-measuring run and the runs tiled "
                          "with its costs")
     ap.add_argument("--reps", type=int, default=5,
-                    help="further runs of K steps for the run-latency "
-                         "percentiles")
+                    help="further runs of K steps (the rate is the median "
+                         "run's; the runs give the latency percentiles)")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     metavar="BYTES", help="only run plain copies of BYTES")
     ap.add_argument("--window", type=float, default=60.0,
