@@ -112,8 +112,11 @@ std::vector<int2> pack_tiles(const std::vector<int32_t>& lanes,
 
 std::vector<int2> xcd_interleave(const std::vector<int2>& tiles, int domains) {
   const int64_t n = (int64_t)tiles.size();
+  // the first n mod domains chunks hold one tile more, so that the last,
+  // partial round of positions is exactly those chunks' XCDs
+  const int64_t q = n / domains, rem = n % domains;
   std::vector<int64_t> start(domains + 1);
-  for (int x = 0; x <= domains; ++x) start[x] = n * x / domains;
+  for (int x = 0; x <= domains; ++x) start[x] = q * x + std::min<int64_t>(x, rem);
   std::vector<int2> out;
   out.reserve(n);
   for (int64_t r = 0;; ++r) {
