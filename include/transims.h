@@ -10,11 +10,11 @@
  * gap / random slowdown / move (rules i-iii), a lane-change sub-step before
  * the forward move, unsignalised intersections with priority (gap acceptance
  * on the priority street), and vehicles entering from and exiting to parking
- * along precomputed routes.  The update order follows the paper's sequence
- * "change lanes, exchange boundaries, compute speeds and move, exchange"
- * (Section "Micro-simulation parallelization: Domain decomposition"); on one
- * GPU the two boundary exchanges become kernel boundaries plus in-memory
- * handoff slots.
+ * along precomputed routes.  The update order follows the paper's per-step
+ * sequence: lane-change sub-step, boundary exchange, velocity-and-move
+ * sub-step, boundary exchange (Section "Micro-simulation parallelization:
+ * Domain decomposition"); on one GPU the two boundary exchanges become
+ * kernel boundaries plus in-memory handoff slots.
  *
  * Rules the paper leaves open are fixed as follows (the same readings bind
  * every implementation that claims to compute this step):

@@ -23,7 +23,7 @@
  *      threshold slow_thr = floor(p * 2^32), computed exactly on the host.
  *  R4  Ring mode: one periodic lane of L cells; gap is measured cyclically;
  *      a lone vehicle sees gap L-1.
- *  R5  Vehicles leave parking (paper: "enter the simulation from parking")
+ *  R5  Vehicles leave parking and enter the network
  *      at cell 0 of the first route link, into the lowest lane whose cell 0
  *      is empty, with v = 0; per link a FIFO ordered by (depart, id); at most
  *      one per link per step; a blocked head blocks the queue.
@@ -57,7 +57,7 @@
  *      5-cell interaction range.
  *  R8  A vehicle that passes the link end lands at cell x+v3-len of lane k'
  *      of the next link; exit_t[route entry of the link it left] = t.  On
- *      the last link it is removed (ARRIVED, "exit to parking").
+ *      the last link it is removed (ARRIVED: back into parking).
  *
  * Signalised turns (same section: a virtual vehicle of maximum speed zero
  * stands at the end of the lane while the light is red):

@@ -1,10 +1,10 @@
 // front_back.hip -- the two-kernel form of the TRANSIMS per-second update
 // (gfx950), used with lane changes or short links.
 //
-// A step is two kernels, the GPU form of the paper's update sequence
-// "change lanes / exchange / compute speeds and move / exchange" (Section
-// "Micro-simulation parallelization: Domain decomposition"): the kernel
-// boundaries are the two exchanges.  Each workgroup is one wavefront that
+// A step is two kernels, the GPU form of the paper's per-step sequence of a
+// lane-change sub-step and a velocity-and-move sub-step, each followed by a
+// boundary exchange (Section "Micro-simulation parallelization: Domain
+// decomposition"): the kernel boundaries are the two exchanges.  Each workgroup is one wavefront that
 // owns a tile of whole links (at most 64 lanes); a lane's vehicles live in a
 // lead-first ring buffer, so the per-step traffic is proportional to the
 // vehicles, not to the cells.
