@@ -276,7 +276,8 @@ hipError_t launch_stats(const DevScen* d_desc, unsigned long long* d_out,
 }
 
 hipError_t launch_export(const DevScen* d_desc, ExportBufs out, int n_veh,
-                         int n_links, int n_lanes, int ring, hipStream_t s) {
+                         int /*n_links*/, int n_lanes, int ring,
+                         hipStream_t s) {
   (void)hipGetLastError();
   if (n_veh > 0)
     hipLaunchKernelGGL(k_export_fill, dim3((n_veh + 255) / 256), dim3(256), 0,

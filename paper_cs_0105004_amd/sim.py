@@ -9,7 +9,7 @@ from __future__ import annotations
 
 import ctypes as C
 import os
-from typing import Dict, Iterable, Optional
+from typing import Dict, Optional
 
 import numpy as np
 

@@ -4,7 +4,6 @@ departing at once, four lanes everywhere, the longest links the library
 accepts (also with lane changes, whose bit lattice of a 4-lane link of
 32,767 cells takes 4,096 words of LDS), the smallest grid, and a scenario
 with no vehicles at all."""
-import numpy as np
 import pytest
 
 import oracle

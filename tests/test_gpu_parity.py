@@ -1,9 +1,7 @@
 """GPU parity: libtransims (through its C ABI) against the CPU oracle, bit
 for bit, on the same seeded inputs.  Every step is integer, so the bar is
 exact equality of every vehicle's state, every exit time and every counter."""
-import dataclasses
 
-import numpy as np
 import pytest
 
 import oracle

@@ -2,11 +2,9 @@
 the GPU: the deterministic ring's closed form at every density, and the
 qualitative shape of the other diagrams; one merge scenario against the
 oracle."""
-import numpy as np
 import pytest
 
 import oracle
-from paper_cs_0105004_amd import scenarios as S
 from paper_cs_0105004_amd import validation as V
 from parity import assert_same_state, assert_same_stats
 
