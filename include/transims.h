@@ -195,7 +195,10 @@ sim_status sim_load_network(sim_ctx* ctx, int32_t slot, const sim_params* p,
                             uint64_t ws_bytes);
 
 /* Loads vehicles and routes into a slot holding a network.  Synchronises
-   the context stream before returning. */
+   the context stream before returning.  The routes also set the order in
+   which each XCD's tiles are launched: heaviest first by planned load (the
+   routes using a link times its cells), which shortens a launch's tail and
+   leaves every result unchanged. */
 sim_status sim_load_vehicles(sim_ctx* ctx, int32_t slot,
                              const sim_vehicles* veh);
 
