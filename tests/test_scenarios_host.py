@@ -1,0 +1,100 @@
+"""The seeded input generators against the recipes they stand for: the
+Portland-sized grid's sizes and ranges, strong connectivity, connected
+routes between distinct nodes; the 200k-link recipe's ranges
+(at 1/100 scale); the batch's link-count and demand ranges; the ring; and
+determinism in the seed."""
+import numpy as np
+import pytest
+from scipy.sparse import csr_matrix
+from scipy.sparse.csgraph import connected_components
+
+from paper_cs_0105004_amd import scenarios as S
+
+
+def strongly_connected(n_nodes, frm, to):
+    g = csr_matrix((np.ones(len(frm)), (frm, to)), shape=(n_nodes, n_nodes))
+    n, _ = connected_components(g, directed=True, connection="strong")
+    return n == 1
+
+
+def check_routes(sc):
+    off, rl = sc.route_off, sc.route_links
+    assert off[0] == 0 and off[-1] == len(rl)
+    assert (np.diff(off) >= 1).all()
+    # consecutive links of a route meet at a node
+    first = np.zeros(len(rl), bool)
+    first[off[:-1]] = True
+    prev = np.roll(rl, 1)
+    joined = sc.link_to[prev] == sc.link_from[rl]
+    assert joined[~first].all()
+    orig = sc.link_from[rl[off[:-1]]]
+    dest = sc.link_to[rl[off[1:] - 1]]
+    assert (orig != dest).all()
+
+
+@pytest.fixture(scope="module")
+def c2():
+    return S.portland_like(T=3600)
+
+
+def test_portland_sized_grid_recipe(c2):
+    assert c2.n_nodes == 77 * 78 == 6006
+    assert len(c2.link_from) == 20024
+    assert c2.link_lanes.min() >= 1 and c2.link_lanes.max() <= 3
+    assert c2.link_len.min() >= 20 and c2.link_len.max() <= 200
+    assert c2.n_veh == 200000
+    assert c2.depart.min() >= 0 and c2.depart.max() <= 1799
+    assert c2.vmax == 5 and c2.slow_thr == S.prob_threshold("0.2")
+    assert c2.flags == 0 and c2.T == 3600
+    # links come in opposite pairs of one length (undirected edges)
+    pairs = {}
+    for f, t, ln in zip(c2.link_from, c2.link_to, c2.link_len):
+        pairs[(int(f), int(t))] = int(ln)
+    assert all(pairs.get((t, f)) == ln for (f, t), ln in pairs.items())
+    assert strongly_connected(c2.n_nodes, c2.link_from, c2.link_to)
+    check_routes(c2)
+
+
+def test_large_network_recipe_at_small_scale():
+    sc = S.large_network(scale=0.01, T=600)
+    assert sc.link_lanes.min() >= 1 and sc.link_lanes.max() <= 4
+    assert sc.link_len.min() >= 6 and sc.link_len.max() <= 1000
+    assert sc.depart.min() >= 0 and sc.depart.max() <= 599
+    assert sc.flags == S.FLAG_LANE_CHANGE | S.FLAG_TURN_LANES
+    assert sc.n_veh == 20000
+    assert strongly_connected(sc.n_nodes, sc.link_from, sc.link_to)
+    check_routes(sc)
+    # lengths: lognormal with median 60 cells
+    assert 45 <= np.median(sc.link_len) <= 75
+
+
+def test_batch_recipe():
+    scens = S.batched_scenarios(n=4, T=300, scale=0.05)
+    for k, sc in enumerate(scens):
+        links = len(sc.link_from)
+        assert sc.n_veh >= 5 * links and sc.n_veh <= 15 * links
+        assert sc.seed == 1000 + k
+        assert sc.depart.max() <= 1799
+        assert strongly_connected(sc.n_nodes, sc.link_from, sc.link_to)
+        check_routes(sc)
+
+
+def test_ring_recipe():
+    sc = S.ring()
+    assert sc.link_len[0] == 1000 and sc.n_veh == 150 and sc.seed == 42
+    assert sc.vmax == 5 and sc.slow_thr == 858993459 and sc.T == 1000
+    x = sc.init_x
+    assert len(np.unique(x)) == 150 and x.min() >= 0 and x.max() < 1000
+    assert (sc.init_v == 0).all()
+    # vehicles are listed in cell order, one per cell
+    assert (np.diff(x) > 0).all()
+
+
+def test_generators_are_deterministic_in_the_seed():
+    a = S.portland_like(scale=0.02, T=200, seed=5)
+    b = S.portland_like(scale=0.02, T=200, seed=5)
+    c = S.portland_like(scale=0.02, T=200, seed=6)
+    for f in ("link_from", "link_to", "link_len", "link_lanes", "depart",
+              "route_off", "route_links"):
+        np.testing.assert_array_equal(getattr(a, f), getattr(b, f))
+    assert not np.array_equal(a.route_links, c.route_links)
