@@ -54,7 +54,8 @@ typedef enum {
   SIM_E_NOMEM = -2,    /* the caller's workspace is smaller than needed      */
   SIM_E_STATE = -3,    /* wrong call order, or slot not loaded               */
   SIM_E_DEVICE = -4,   /* HIP runtime error, or sticky device error bits     */
-  SIM_E_CAPACITY = -5, /* a size exceeds a library limit                     */
+  SIM_E_CAPACITY = -5, /* a size exceeds a library limit, or host memory ran
+                          out (no C++ exception crosses this interface)     */
   SIM_E_ABI = -6       /* abi_version mismatch                               */
 } sim_status;
 
@@ -198,7 +199,10 @@ sim_status sim_load_network(sim_ctx* ctx, int32_t slot, const sim_params* p,
    the context stream before returning.  The routes also set the order in
    which each XCD's tiles are launched: heaviest first by planned load (the
    routes using a link times its cells), which shortens a launch's tail and
-   leaves every result unchanged. */
+   leaves every result unchanged.  The input is checked on the host
+   (route_off starts at 0 and rises strictly, routes connect, placements fit)
+   before it is used; on any error the slot holds no vehicles and must be
+   loaded again before it is stepped. */
 sim_status sim_load_vehicles(sim_ctx* ctx, int32_t slot,
                              const sim_vehicles* veh);
 

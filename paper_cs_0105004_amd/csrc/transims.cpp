@@ -9,6 +9,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <exception>
 #include <new>
 #include <numeric>
 #include <string>
@@ -285,6 +286,21 @@ sim_status check_slot(sim_ctx* c, int32_t slot) {
   return SIM_OK;
 }
 
+// Route offsets of n vehicles: route_off[0] = 0 and strictly rising (every
+// route holds at least one link), so that every route lies inside
+// [0, route_off[n]).
+sim_status check_route_off(sim_ctx* c, int32_t n, const int64_t* route_off) {
+  if (n == 0) return SIM_OK;
+  if (!route_off) return fail(c, SIM_E_INVAL, "route_off is NULL");
+  if (route_off[0] != 0) return fail(c, SIM_E_INVAL, "route_off[0] must be 0");
+  for (int32_t i = 0; i < n; ++i)
+    if (route_off[i + 1] <= route_off[i])
+      return fail(c, SIM_E_INVAL, "vehicle %d: empty route", i);
+  if (route_off[n] > INT32_MAX - 2)
+    return fail(c, SIM_E_CAPACITY, "too many route entries");
+  return SIM_OK;
+}
+
 template <class T>
 hipError_t up(T* dst, const T* src, int64_t n, hipStream_t s) {
   if (n <= 0) return hipSuccess;
@@ -295,7 +311,7 @@ hipError_t up(T* dst, const T* src, int64_t n, hipStream_t s) {
 
 // ---------------------------------------------------------------------------
 
-extern "C" sim_status sim_create(const sim_config* cfg, sim_ctx** out) {
+static sim_status create_body(const sim_config* cfg, sim_ctx** out) {
   if (!cfg || !out) return SIM_E_INVAL;
   *out = nullptr;
   if (cfg->abi_version != SIM_ABI_VERSION) return SIM_E_ABI;
@@ -312,7 +328,12 @@ extern "C" sim_status sim_create(const sim_config* cfg, sim_ctx** out) {
   if (c->cfg.back_pieces == 0) c->cfg.back_pieces = kDefaultBackPieces;
   if (c->cfg.graph_steps == 0) c->cfg.graph_steps = kDefaultGraphSteps;
   c->stream = reinterpret_cast<hipStream_t>(cfg->stream);
-  c->slots.resize(cfg->max_slots);
+  try {
+    c->slots.resize(cfg->max_slots);
+  } catch (const std::bad_alloc&) {
+    delete c;
+    return SIM_E_CAPACITY;
+  }
   if (hipGetDevice(&c->device) != hipSuccess ||
       hipMalloc(&c->d_descs, sizeof(DevScen) * cfg->max_slots) != hipSuccess ||
       hipMalloc(&c->d_stats, sizeof(unsigned long long) * (C_N + 3)) !=
@@ -343,9 +364,9 @@ extern "C" const char* sim_last_error(const sim_ctx* c) {
   return c ? c->err.c_str() : "no context";
 }
 
-extern "C" sim_status sim_footprint(const sim_ctx* cc, const sim_params* p,
-                                    const sim_network* net,
-                                    const sim_vehicles* veh, uint64_t* bytes) {
+static sim_status footprint_body(const sim_ctx* cc, const sim_params* p,
+                                 const sim_network* net,
+                                 const sim_vehicles* veh, uint64_t* bytes) {
   sim_ctx* c = const_cast<sim_ctx*>(cc);
   if (!bytes) return fail(c, SIM_E_INVAL, "bytes is NULL");
   sim_status st = check_params(c, p);
@@ -357,17 +378,18 @@ extern "C" sim_status sim_footprint(const sim_ctx* cc, const sim_params* p,
   carve_network(cv, net_dims(p, net, c ? c->cfg.back_pieces : kDefaultBackPieces), d, ring);
   if (veh) {
     if (veh->n < 0) return fail(c, SIM_E_INVAL, "negative vehicle count");
-    const int64_t R = (!ring && veh->route_off) ? veh->route_off[veh->n] : 0;
+    if (!ring && (st = check_route_off(c, veh->n, veh->route_off)) != SIM_OK) return st;
+    const int64_t R = (!ring && veh->n > 0) ? veh->route_off[veh->n] : 0;
     carve_vehicles(cv, veh->n, R, d, ring);
   }
   *bytes = cv.off + 256;
   return SIM_OK;
 }
 
-extern "C" sim_status sim_load_network(sim_ctx* c, int32_t slot,
-                                       const sim_params* p,
-                                       const sim_network* net, void* dev_ws,
-                                       uint64_t ws_bytes) {
+static sim_status load_network_body(sim_ctx* c, int32_t slot,
+                                    const sim_params* p,
+                                    const sim_network* net, void* dev_ws,
+                                    uint64_t ws_bytes) {
   sim_status st = check_slot(c, slot);
   if (st != SIM_OK) return st;
   if ((st = check_params(c, p)) != SIM_OK) return st;
@@ -563,13 +585,17 @@ extern "C" sim_status sim_load_network(sim_ctx* c, int32_t slot,
   return SIM_OK;
 }
 
-extern "C" sim_status sim_load_vehicles(sim_ctx* c, int32_t slot,
-                                        const sim_vehicles* v) {
+static sim_status load_vehicles_body(sim_ctx* c, int32_t slot,
+                                     const sim_vehicles* v) {
   sim_status st = check_slot(c, slot);
   if (st != SIM_OK) return st;
   Slot& S = c->slots[slot];
   if (!S.net) return fail(c, SIM_E_STATE, "slot %d has no network", slot);
   if (!v || v->n < 0) return fail(c, SIM_E_INVAL, "bad vehicles");
+  // the per-run device state is reset below: until this load succeeds the
+  // slot holds no vehicles and cannot be stepped
+  S.veh = false;
+  c->work_key.clear();
   const int32_t n = v->n;
   const int vmax = S.p.vmax;
   if (n > 0 && !v->depart) return fail(c, SIM_E_INVAL, "depart is NULL");
@@ -578,6 +604,8 @@ extern "C" sim_status sim_load_vehicles(sim_ctx* c, int32_t slot,
   if (has_init && (!v->init_lane || !v->init_x || !v->init_v ||
                    (!S.ring && !v->init_rptr)))
     return fail(c, SIM_E_INVAL, "incomplete initial state arrays");
+  if (!S.ring && (st = check_route_off(c, n, v->route_off)) != SIM_OK) return st;
+  if (!S.ring && n > 0 && !v->route_links) return fail(c, SIM_E_INVAL, "route_links is NULL");
   DevScen& d = S.d;
   hipStream_t s = c->stream;
   // per-run device state starts empty
@@ -637,11 +665,7 @@ extern "C" sim_status sim_load_vehicles(sim_ctx* c, int32_t slot,
     S.n_route = 0;
     d.n_route = 0;
   } else {
-    if (n > 0 && (!v->route_off || !v->route_links))
-      return fail(c, SIM_E_INVAL, "routes are NULL");
-    const int64_t R = n > 0 ? v->route_off[n] : 0;
-    if (n > 0 && v->route_off[0] != 0) return fail(c, SIM_E_INVAL, "route_off[0] must be 0");
-    if (R > INT32_MAX - 2) return fail(c, SIM_E_CAPACITY, "too many route entries");
+    const int64_t R = n > 0 ? v->route_off[n] : 0;  // offsets checked above
     const int32_t L = S.n_links;
     const bool turn = S.p.flags & SIM_FLAG_TURN_LANES;
     // route entries as internal link ids, then as route info words
@@ -649,7 +673,6 @@ extern "C" sim_status sim_load_vehicles(sim_ctx* c, int32_t slot,
     std::vector<uint32_t> rinfo(R);
     for (int32_t i = 0; i < n; ++i) {
       const int64_t a = v->route_off[i], b = v->route_off[i + 1];
-      if (b <= a) return fail(c, SIM_E_INVAL, "vehicle %d: empty route", i);
       for (int64_t j = a; j < b; ++j) {
         const int32_t e = v->route_links[j];
         if (e < 0 || e >= L) return fail(c, SIM_E_INVAL, "vehicle %d: route link out of range", i);
@@ -1093,8 +1116,8 @@ extern "C" sim_status sim_kernel_times(sim_ctx* c, sim_kernel_time out[4]) {
   return SIM_OK;
 }
 
-extern "C" sim_status sim_step(sim_ctx* c, const int32_t* slots, int32_t n_slots,
-                               int32_t n_steps) {
+static sim_status step_body(sim_ctx* c, const int32_t* slots, int32_t n_slots,
+                            int32_t n_steps) {
   if (!c) return SIM_E_INVAL;
   if (!slots || n_slots < 1) return fail(c, SIM_E_INVAL, "no slots");
   if (n_steps < 0) return fail(c, SIM_E_INVAL, "negative step count");
@@ -1224,9 +1247,9 @@ extern "C" sim_status sim_stats(sim_ctx* c, int32_t slot, sim_stats_t* out) {
   return SIM_OK;
 }
 
-extern "C" sim_status sim_read_state(sim_ctx* c, int32_t slot, int8_t* status,
-                                     int32_t* link, int8_t* lane, int32_t* x,
-                                     int8_t* v, int32_t* rptr, int32_t* exit_t) {
+static sim_status read_state_body(sim_ctx* c, int32_t slot, int8_t* status,
+                                  int32_t* link, int8_t* lane, int32_t* x,
+                                  int8_t* v, int32_t* rptr, int32_t* exit_t) {
   sim_status st = check_slot(c, slot);
   if (st != SIM_OK) return st;
   const Slot& S = c->slots[slot];
@@ -1273,7 +1296,7 @@ extern "C" sim_status sim_read_state(sim_ctx* c, int32_t slot, int8_t* status,
   return SIM_OK;
 }
 
-extern "C" sim_status sim_link_costs(sim_ctx* c, int32_t slot, float* out) {
+static sim_status link_costs_body(sim_ctx* c, int32_t slot, float* out) {
   sim_status st = check_slot(c, slot);
   if (st != SIM_OK) return st;
   const Slot& S = c->slots[slot];
@@ -1333,4 +1356,65 @@ extern "C" sim_status sim_unload(sim_ctx* c, int32_t slot) {
   c->slots[slot] = Slot();
   c->work_key.clear();
   return SIM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// The entry points that build host tables: a C++ exception (host memory
+// exhausted) becomes an error status instead of crossing the C boundary.
+
+namespace {
+
+template <class F>
+sim_status guarded(const sim_ctx* cc, F&& body) {
+  sim_ctx* c = const_cast<sim_ctx*>(cc);
+  try {
+    return body();
+  } catch (const std::bad_alloc&) {
+    return fail(c, SIM_E_CAPACITY, "host memory exhausted");
+  } catch (const std::exception& e) {
+    return fail(c, SIM_E_INVAL, "%s", e.what());
+  }
+}
+
+}  // namespace
+
+extern "C" sim_status sim_create(const sim_config* cfg, sim_ctx** out) {
+  return guarded(nullptr, [&] { return create_body(cfg, out); });
+}
+
+extern "C" sim_status sim_footprint(const sim_ctx* cc, const sim_params* p,
+                                    const sim_network* net,
+                                    const sim_vehicles* veh, uint64_t* bytes) {
+  return guarded(cc, [&] { return footprint_body(cc, p, net, veh, bytes); });
+}
+
+extern "C" sim_status sim_load_network(sim_ctx* c, int32_t slot,
+                                       const sim_params* p,
+                                       const sim_network* net, void* dev_ws,
+                                       uint64_t ws_bytes) {
+  return guarded(c, [&] {
+    return load_network_body(c, slot, p, net, dev_ws, ws_bytes);
+  });
+}
+
+extern "C" sim_status sim_load_vehicles(sim_ctx* c, int32_t slot,
+                                        const sim_vehicles* v) {
+  return guarded(c, [&] { return load_vehicles_body(c, slot, v); });
+}
+
+extern "C" sim_status sim_step(sim_ctx* c, const int32_t* slots, int32_t n_slots,
+                               int32_t n_steps) {
+  return guarded(c, [&] { return step_body(c, slots, n_slots, n_steps); });
+}
+
+extern "C" sim_status sim_read_state(sim_ctx* c, int32_t slot, int8_t* status,
+                                     int32_t* link, int8_t* lane, int32_t* x,
+                                     int8_t* v, int32_t* rptr, int32_t* exit_t) {
+  return guarded(c, [&] {
+    return read_state_body(c, slot, status, link, lane, x, v, rptr, exit_t);
+  });
+}
+
+extern "C" sim_status sim_link_costs(sim_ctx* c, int32_t slot, float* out) {
+  return guarded(c, [&] { return link_costs_body(c, slot, out); });
 }
