@@ -79,8 +79,9 @@ typedef struct {
   int32_t back_pieces;  /* wavefronts per tile in the move sub-step, which
                            share the tile's lanes by vehicle load, 1..8;
                            0 = default (4)                                  */
-  int32_t graph_steps;  /* steps per HIP graph replay in sim_step; 0 =
-                           default (64); < 0 = launch kernels one by one    */
+  int32_t graph_steps;  /* steps per HIP graph replay in sim_step, at most
+                           4096; 0 = default (64); < 0 = launch kernels one
+                           by one                                           */
   int32_t step_mode;    /* 0 = one kernel per step for scenarios without
                            lane changes whose links all have >= 2*vmax
                            cells, two kernels (lane-change / move sub-step)
@@ -177,7 +178,9 @@ typedef struct {
   uint32_t reserved2;
 } sim_stats_t;
 
-/* Creates a context on the current HIP device.  *out receives it. */
+/* Creates a context on the current HIP device.  *out receives it.  The
+   configuration is checked before any device call: a field out of its
+   stated range returns SIM_E_INVAL, another abi_version SIM_E_ABI. */
 sim_status sim_create(const sim_config* cfg, sim_ctx** out);
 
 /* Bytes of device workspace that sim_load_network + sim_load_vehicles need

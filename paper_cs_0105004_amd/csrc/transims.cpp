@@ -143,6 +143,7 @@ struct NetDims {
 };
 
 constexpr int64_t kExtraRunsMax = 1024;  // extra move wavefronts per step
+constexpr int32_t kMaxGraphSteps = 4096;  // steps per HIP graph
 
 // entries of the list of extra move wavefronts for `tiles` tiles
 int64_t extra_cap(int64_t tiles, int pieces) {
@@ -319,6 +320,7 @@ static sim_status create_body(const sim_config* cfg, sim_ctx** out) {
   if (cfg->tile_lanes < 0 || cfg->tile_lanes > kMaxTileLanes) return SIM_E_INVAL;
   if (cfg->back_pieces < 0 || cfg->back_pieces > 8) return SIM_E_INVAL;
   if (cfg->step_mode < 0 || cfg->step_mode > 1) return SIM_E_INVAL;
+  if (cfg->graph_steps > kMaxGraphSteps) return SIM_E_INVAL;
   if (cfg->tile_cells != 0 && (cfg->tile_cells < 64 || cfg->tile_cells > 65536))
     return SIM_E_INVAL;
   if (cfg->reserved != 0) return SIM_E_INVAL;

@@ -107,3 +107,27 @@ def test_network_checks(lib, scen):
 def test_parameter_checks(lib, scen):
     for kw in ({"vmax": 0}, {"vmax": 8}):
         assert footprint(lib, dataclasses.replace(scen, **kw))[0] == sim.E_INVAL
+
+
+def test_context_configuration_checks(lib):
+    # sim_create checks its configuration before any device call, so these
+    # are refused the same way with or without a GPU
+    def create(**kw):
+        f = dict(abi_version=sim.ABI_VERSION, max_slots=1, stream=None,
+                 tile_lanes=0, back_pieces=0, graph_steps=0, step_mode=0,
+                 tile_cells=0, reserved=0)
+        f.update(kw)
+        cfg = sim.sim_config(**f)
+        h = C.c_void_p()
+        rc = lib.sim_create(C.byref(cfg), C.byref(h))
+        if rc == sim.OK:
+            lib.sim_destroy(h)
+        return rc
+
+    assert create(abi_version=sim.ABI_VERSION + 1) == sim.E_ABI
+    for kw in ({"max_slots": 0}, {"max_slots": 65537}, {"tile_lanes": -1},
+               {"tile_lanes": 65}, {"back_pieces": 9}, {"back_pieces": -1},
+               {"step_mode": 2}, {"tile_cells": 63}, {"tile_cells": 65537},
+               {"graph_steps": 4097}, {"reserved": 1}):
+        assert create(**kw) == sim.E_INVAL, kw
+    assert lib.sim_create(None, None) == sim.E_INVAL
