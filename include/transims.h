@@ -221,14 +221,18 @@ sim_status sim_stats(sim_ctx* ctx, int32_t slot, sim_stats_t* out);
 
 /* Waits for the stream and copies the per-vehicle state to host arrays of
    n entries (any may be NULL): status, link (-1 unless ACTIVE), lane, x, v,
-   rptr; exit_t receives route_off[n] entries. */
+   rptr; exit_t receives route_off[n] entries.  The export goes through a
+   temporary device buffer of 15 bytes per vehicle, allocated and freed
+   inside the call. */
 sim_status sim_read_state(sim_ctx* ctx, int32_t slot, int8_t* status,
                           int32_t* link, int8_t* lane, int32_t* x, int8_t* v,
                           int32_t* rptr, int32_t* exit_t);
 
-/* Measured cost per link (device clock cycles spent on the link's tile,
-   shared out by cells), for use as net->link_cost of a later run (adaptive
-   load balancing). out has n_links entries. */
+/* Waits for the stream and reports the measured cost per link (device
+   clock cycles spent on the link's tile since the vehicles were loaded,
+   shared out by cells), for use as net->link_cost of a later run: the
+   paper's adaptive load balancing, which re-partitions by the load measured
+   in the run before.  out has n_links entries, in the caller's link order. */
 sim_status sim_link_costs(sim_ctx* ctx, int32_t slot, float* out);
 
 typedef struct {
@@ -239,6 +243,10 @@ typedef struct {
   double e_tile;     /* mean / max weight over tiles                       */
 } sim_tiling;
 
+/* The decomposition of the slot's network into workgroup tiles and its
+   balance: e_dmn is the paper's partition efficiency (Section "Graph
+   partitioning": the load of an ideal split over the load of the largest
+   part), taken over the 8 XCDs; e_tile is the same over the tiles. */
 sim_status sim_tiling_info(const sim_ctx* ctx, int32_t slot, sim_tiling* out);
 
 /* Kernel timing (the paper monitors the time per step, Section "Adaptive
