@@ -68,26 +68,32 @@ class _Stats(C.Structure):
 _lib = None
 
 
+def bind(path: str) -> C.CDLL:
+    """Loads an oracle library built from transims_oracle.c at `path` and
+    declares its signatures."""
+    L = C.CDLL(path)
+    L.orc_create.restype = C.c_void_p
+    L.orc_create.argtypes = [C.POINTER(_Params), C.POINTER(_Network),
+                             C.POINTER(_Vehicles), C.c_char_p, C.c_int]
+    L.orc_destroy.argtypes = [C.c_void_p]
+    L.orc_step.argtypes = [C.c_void_p, C.c_int32]
+    L.orc_step.restype = C.c_int
+    L.orc_get_stats.argtypes = [C.c_void_p, C.POINTER(_Stats)]
+    L.orc_get_state.argtypes = [C.c_void_p] + [C.c_void_p] * 7
+    L.orc_philox4x32_10.argtypes = [C.c_void_p] * 3
+    L.orc_philox4x64_10.argtypes = [C.c_void_p] * 3
+    L.orc_mix64.argtypes = [C.c_uint64]
+    L.orc_mix64.restype = C.c_uint64
+    return L
+
+
 def lib():
     global _lib
     if _lib is None:
         if not os.path.exists(_LIB_PATH) or (
                 os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC)):
             build()
-        L = C.CDLL(_LIB_PATH)
-        L.orc_create.restype = C.c_void_p
-        L.orc_create.argtypes = [C.POINTER(_Params), C.POINTER(_Network),
-                                 C.POINTER(_Vehicles), C.c_char_p, C.c_int]
-        L.orc_destroy.argtypes = [C.c_void_p]
-        L.orc_step.argtypes = [C.c_void_p, C.c_int32]
-        L.orc_step.restype = C.c_int
-        L.orc_get_stats.argtypes = [C.c_void_p, C.POINTER(_Stats)]
-        L.orc_get_state.argtypes = [C.c_void_p] + [C.c_void_p] * 7
-        L.orc_philox4x32_10.argtypes = [C.c_void_p] * 3
-        L.orc_philox4x64_10.argtypes = [C.c_void_p] * 3
-        L.orc_mix64.argtypes = [C.c_uint64]
-        L.orc_mix64.restype = C.c_uint64
-        _lib = L
+        _lib = bind(_LIB_PATH)
     return _lib
 
 

@@ -7,14 +7,15 @@ import numpy as np
 
 from paper_cs_0105004_amd import scenarios as S
 
-PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
-                    "hand_cases.json")
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+PATH = os.path.join(GOLDEN, "hand_cases.json")
+BOUNDARIES = os.path.join(GOLDEN, "hand_cases_boundaries.json")
 FLAGS = {"LANE_CHANGE": S.FLAG_LANE_CHANGE, "TURN_LANES": S.FLAG_TURN_LANES}
 STATUS = {"waiting": S.WAITING, "active": S.ACTIVE, "arrived": S.ARRIVED}
 
 
-def load_cases():
-    with open(PATH) as f:
+def load_cases(path=PATH):
+    with open(path) as f:
         return json.load(f)["cases"]
 
 

@@ -1,0 +1,94 @@
+"""The hand-worked cases against planted mistakes in the oracle.
+
+Each mutant below is the oracle with one plausible slip: a strict
+comparison made non-strict, a dropped term, an off-by-one, a swapped order.
+It is compiled on its own (the oracle's library is left alone) and run
+over the hand-worked cases of tests/golden/; at least one case must
+notice.  This is what makes the cases pins rather than a copy of the
+oracle's behaviour: a mistake at any of these places would change an
+outcome that was worked out by hand."""
+import os
+import subprocess
+
+import pytest
+
+import oracle
+from hand_cases import BOUNDARIES, build, check, load_cases
+
+ORACLE_DIR = os.path.dirname(os.path.abspath(oracle.__file__))
+SRC = os.path.join(ORACLE_DIR, "transims_oracle.c")
+
+MUTANTS = [
+    ("incentive_non_strict",  # ahead(own) < min(v+1, vmax) read as <=
+     "if (own >= want) return -1;", "if (own > want) return -1;"),
+    ("incentive_wants_v",  # min(v+1, vmax) read as min(v, vmax)
+     "int32_t want = v + 1 < vmax ? v + 1 : vmax;",
+     "int32_t want = v < vmax ? v : vmax;"),
+    ("side_gap_not_strict",  # ahead(m) > ahead(own) read as >=
+     "if (a <= own) continue;", "if (a < own) continue;"),
+    ("gap_behind_short_by_one",
+     "if (behind(s, l, m, x) < vmax) continue;",
+     "if (behind(s, l, m, x) < vmax - 1) continue;"),
+    ("side_cell_not_checked",
+     "if (*cell(s, l, m, x) >= 0) continue;", "if (0) continue;"),
+    ("ties_go_right",
+     "int32_t sides[2] = {k - 1, k + 1};", "int32_t sides[2] = {k + 1, k - 1};"),
+    ("conflict_not_resolved",
+     "if (j >= 0 && s->dec[j] == m) s->dec[i] = -1;", "if (0) s->dec[i] = -1;"),
+    ("desperation_non_strict",
+     "behind(s, l, m, x) >= need) return m;",
+     "behind(s, l, m, x) > need) return m;"),
+    ("desperation_distance_off_by_one",
+     "int32_t need = (s->len[l] - 1 - x) / s->p.lc_desp;",
+     "int32_t need = (s->len[l] - x) / s->p.lc_desp;"),
+    ("desperation_cell_not_checked",
+     "if (*cell(s, l, m, x) < 0 && behind(s, l, m, x) >= need) return m;",
+     "if (behind(s, l, m, x) >= need) return m;"),
+    ("winner_extra_off_by_one",
+     "s->extra[i] = s->rear_x[tq] < vmax ? s->rear_x[tq] : vmax;",
+     "s->extra[i] = s->rear_x[tq] + 1 < vmax ? s->rear_x[tq] + 1 : vmax;"),
+    ("node_key_lane_before_rank",
+     "int32_t key = s->rank[l] * 8 + k;", "int32_t key = k * 8 + s->rank[l];"),
+    ("loser_keeps_room",  # every candidate, not only the winner, gets extra
+     "} else if (key == s->best[tq]) {", "} else {"),
+    ("trip_end_without_extra",
+     "s->extra[i] = vmax;\n          continue;", "continue;"),
+    ("gap_counts_the_vehicle_ahead",
+     "gap = c - x - 1;", "gap = c - x;"),
+    ("parking_highest_lane_first",
+     "for (int32_t k = 0; k < s->lanes[l]; ++k) {\n      int32_t* c = cell(s, l, k, 0);",
+     "for (int32_t k = s->lanes[l] - 1; k >= 0; --k) {\n      int32_t* c = cell(s, l, k, 0);"),
+    ("parking_one_step_late",
+     "if (s->depart[i] > t) continue;", "if (s->depart[i] >= t) continue;"),
+    ("crossing_lands_one_cell_short",
+     "      x -= s->len[l];\n", "      x -= s->len[l] + 1;\n"),
+]
+
+
+@pytest.fixture(scope="module")
+def cases():
+    return load_cases() + load_cases(BOUNDARIES)
+
+
+@pytest.mark.parametrize("name,old,new", MUTANTS, ids=[m[0] for m in MUTANTS])
+def test_each_planted_mistake_fails_a_hand_case(name, old, new, cases,
+                                                tmp_path, monkeypatch):
+    with open(SRC) as f:
+        src = f.read()
+    assert src.count(old) == 1, f"{name}: the oracle no longer reads {old!r}"
+    c_file, so = tmp_path / "mutant.c", tmp_path / "mutant.so"
+    c_file.write_text(src.replace(old, new))
+    subprocess.check_call(["gcc", "-O1", "-std=c11", "-fPIC", "-shared",
+                           "-I", ORACLE_DIR, "-o", str(so), str(c_file)])
+    monkeypatch.setattr(oracle, "_lib", oracle.bind(str(so)))
+    noticed = []
+    for case in cases:
+        o = oracle.OracleSim(build(case))
+        try:
+            o.step(case["steps"])
+            check(case, o.state(), o.stats())
+        except (AssertionError, oracle.OracleError):
+            noticed.append(case["name"])
+        finally:
+            o.close()
+    assert noticed, f"no hand-worked case notices {name}"

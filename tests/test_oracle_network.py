@@ -7,10 +7,11 @@ import pytest
 import oracle
 from paper_cs_0105004_amd import scenarios as S
 
-from hand_cases import build, check, load_cases
+from hand_cases import BOUNDARIES, build, check, load_cases
 
 
-@pytest.mark.parametrize("case", load_cases(), ids=lambda c: c["name"])
+@pytest.mark.parametrize("case", load_cases() + load_cases(BOUNDARIES),
+                         ids=lambda c: c["name"])
 def test_hand_worked_cases(case):
     o = oracle.OracleSim(build(case))
     o.step(case["steps"])
