@@ -88,12 +88,19 @@ def bind(path: str) -> C.CDLL:
 
 
 def lib():
+    """The oracle library: oracle/libtransims_oracle.so, rebuilt when its
+    source is newer; a test that runs the pins against a planted mistake
+    names a mutant build in TRANSIMS_ORACLE_LIB instead."""
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB_PATH) or (
-                os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC)):
-            build()
-        _lib = bind(_LIB_PATH)
+        mutant = os.environ.get("TRANSIMS_ORACLE_LIB")
+        if mutant:
+            _lib = bind(mutant)
+        else:
+            if not os.path.exists(_LIB_PATH) or (
+                    os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC)):
+                build()
+            _lib = bind(_LIB_PATH)
     return _lib
 
 

@@ -1,4 +1,4 @@
-"""The hand-worked cases against planted mistakes in the oracle.
+"""The oracle's pins against planted mistakes in the oracle.
 
 Each mutant below is the oracle with one plausible slip: a strict
 comparison made non-strict, a dropped term, an off-by-one, a swapped order.
@@ -6,7 +6,9 @@ It is compiled on its own (the oracle's library is left alone) and run
 over the hand-worked cases of tests/golden/; at least one case must
 notice.  This is what makes the cases pins rather than a copy of the
 oracle's behaviour: a mistake at any of these places would change an
-outcome that was worked out by hand."""
+outcome that was worked out by hand.  A second set of mutants (the ring,
+the draws, signals, exit times, parking) is run against all of the
+oracle's pins."""
 import os
 import subprocess
 
@@ -92,3 +94,65 @@ def test_each_planted_mistake_fails_a_hand_case(name, old, new, cases,
         finally:
             o.close()
     assert noticed, f"no hand-worked case notices {name}"
+
+
+# Slips elsewhere in the oracle (the ring, the draws, signals, exit times,
+# parking): each mutant must make the rest of the oracle's pins fail.  They
+# run in a child process that loads the mutant through TRANSIMS_ORACLE_LIB.
+RING = "    s->nx[i] = (x + v3) % L;"
+WIDE_MUTANTS = [
+    ("philox_nine_rounds", "for (int r = 0; r < 10; ++r)", "for (int r = 0; r < 9; ++r)"),
+    ("philox_key_bumped_before_round_one", "if (r > 0) {", "if (r >= 0) {"),
+    ("philox_words_crossed", "T n0 = hi1 ^ x1 ^ k0;", "T n0 = hi1 ^ x3 ^ k0;"),
+    ("draw_key_halves_swapped",
+     "uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};",
+     "uint32_t key[2] = {(uint32_t)(seed >> 32), (uint32_t)seed};"),
+    ("ring_slowdown_uses_lane_change_draw",
+     "(uint64_t)draw(s->p.seed, i, t, 1u) < s->p.slow_thr) v3 = v2 - 1;\n"
+     "    s->nv[i] = v3;\n" + RING,
+     "(uint64_t)draw(s->p.seed, i, t, 0u) < s->p.slow_thr) v3 = v2 - 1;\n"
+     "    s->nv[i] = v3;\n" + RING),
+    ("ring_slowdown_at_rest",
+     "if (v2 > 0 && (uint64_t)draw(s->p.seed, i, t, 1u) < s->p.slow_thr) v3 = v2 - 1;\n"
+     "    s->nv[i] = v3;\n" + RING,
+     "if (v2 >= 0 && (uint64_t)draw(s->p.seed, i, t, 1u) < s->p.slow_thr) v3 = v2 - 1;\n"
+     "    s->nv[i] = v3;\n" + RING),
+    ("ring_free_gap_one_short", "int32_t gap = lim;\n", "int32_t gap = lim - 1;\n"),
+    ("ring_gap_counts_the_vehicle_ahead", "gap = d - 1;", "gap = d;"),
+    ("signal_red_one_step_long",
+     "% s->sig_cycle[j]) < s->sig_red[j];", "% s->sig_cycle[j]) <= s->sig_red[j];"),
+    ("signal_offset_subtracted", "(int64_t)t + s->sig_off[j]", "(int64_t)t - s->sig_off[j]"),
+    ("red_light_ignored", "if (is_red(s, l, s->t)) continue;", "if (0) continue;"),
+    ("exit_time_one_late", "s->exit_t[s->route_off[i] + s->rptr[i]] = t;",
+     "s->exit_t[s->route_off[i] + s->rptr[i]] = t + 1;"),
+    ("parking_into_an_occupied_cell",
+     "      if (*c >= 0) continue;\n      *c = i;\n      s->status[i] = ORC_ACTIVE;",
+     "      *c = i;\n      s->status[i] = ORC_ACTIVE;"),
+]
+
+PIN_FILES = ["test_oracle_philox.py", "test_oracle_ring.py",
+             "test_oracle_network.py", "test_oracle_signals.py"]
+
+
+@pytest.mark.parametrize("name,old,new", WIDE_MUTANTS,
+                         ids=[m[0] for m in WIDE_MUTANTS])
+def test_each_planted_mistake_fails_a_pin(name, old, new, tmp_path):
+    import sys
+    with open(SRC) as f:
+        src = f.read()
+    assert src.count(old) == 1, f"{name}: the oracle no longer reads {old!r}"
+    c_file, so = tmp_path / "mutant.c", tmp_path / "mutant.so"
+    c_file.write_text(src.replace(old, new))
+    subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared",
+                           "-I", ORACLE_DIR, "-o", str(so), str(c_file)])
+    here = os.path.dirname(os.path.abspath(__file__))
+    env = dict(os.environ, TRANSIMS_ORACLE_LIB=str(so))
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q",
+                        "-p", "no:cacheprovider", "-m", "not gpu"] +
+                       [os.path.join(here, f) for f in PIN_FILES],
+                       cwd=os.path.dirname(here), env=env,
+                       capture_output=True, text=True, timeout=600)
+    # 1: a pin failed; < 0: a pin failed or the mutant corrupted memory and
+    # the child died of it (either way the mistake was noticed)
+    assert r.returncode == 1 or r.returncode < 0, \
+        f"no pin notices {name} (exit {r.returncode}):\n{r.stdout[-2000:]}"
