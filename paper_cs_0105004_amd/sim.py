@@ -229,17 +229,31 @@ class Context:
         return int(b.value)
 
     def load(self, slot: int, scen, link_cost=None, ws=None):
-        """Allocates the slot's workspace (unless given) and loads scen."""
+        """Allocates the slot's workspace (unless given) and loads scen.  If
+        the library refuses the network or the vehicles, the slot is left
+        empty (a scenario loaded there before is gone too) and SimError is
+        raised."""
         inp = _Inputs(scen, link_cost)
         if ws is None:
             ws = self.torch.empty(self.footprint(scen), dtype=self.torch.uint8,
                                   device="cuda")
-        self._check(self.lib.sim_load_network(
+        rc = self.lib.sim_load_network(
             self.h, slot, C.byref(inp.params), C.byref(inp.net),
-            C.c_void_p(ws.data_ptr()), ws.numel()))
-        self._check(self.lib.sim_load_vehicles(self.h, slot, C.byref(inp.veh)))
-        self.ws[slot] = ws
-        self.scen[slot] = scen
+            C.c_void_p(ws.data_ptr()), ws.numel())
+        if rc == OK:
+            # the slot points into ws from here on: keep ws alive with it
+            self.ws[slot], self.scen[slot] = ws, scen
+            rc = self.lib.sim_load_vehicles(self.h, slot, C.byref(inp.veh))
+            if rc == OK:
+                return
+        msg = (self.lib.sim_last_error(self.h) or b"").decode()
+        if 0 <= slot < self.max_slots:
+            # never leave the library pointing into a workspace that the
+            # binding no longer holds
+            self.lib.sim_unload(self.h, slot)
+            self.ws.pop(slot, None)
+            self.scen.pop(slot, None)
+        raise SimError(rc, msg)
 
     def step(self, slots, n_steps: int = 1):
         if isinstance(slots, int):
