@@ -193,7 +193,7 @@ sim_status sim_footprint(const sim_ctx* ctx, const sim_params* p,
    recursive bisection over link midpoints, weighted by cells or by
    net->link_cost).  dev_ws is device memory owned by the caller that must
    stay valid until sim_unload; the library never frees it.  Any scenario
-   previously in the slot is unloaded. */
+   previously in the slot is unloaded, also when the call fails. */
 sim_status sim_load_network(sim_ctx* ctx, int32_t slot, const sim_params* p,
                             const sim_network* net, void* dev_ws,
                             uint64_t ws_bytes);

@@ -394,11 +394,15 @@ static sim_status load_network_body(sim_ctx* c, int32_t slot,
                                     uint64_t ws_bytes) {
   sim_status st = check_slot(c, slot);
   if (st != SIM_OK) return st;
+  // from here on the slot holds no scenario, also if the call fails; as in
+  // sim_unload, work already enqueued for it finishes first
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  Slot& S = c->slots[slot];
+  S = Slot();
+  c->work_key.clear();
   if ((st = check_params(c, p)) != SIM_OK) return st;
   if ((st = check_network(c, p, net)) != SIM_OK) return st;
   if (!dev_ws) return fail(c, SIM_E_INVAL, "workspace is NULL");
-  Slot& S = c->slots[slot];
-  S = Slot();
   S.p = *p;
   S.ring = p->flags & SIM_FLAG_RING;
   const int32_t L = net->n_links;
