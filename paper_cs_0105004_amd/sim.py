@@ -108,7 +108,13 @@ def load_library() -> C.CDLL:
             "libtransims.so is not built; run paper_cs_0105004_amd/build.py "
             "(or __graft_entry__.build())")
     import torch  # noqa: F401  (maps torch's libamdhip64 first)
-    L = C.CDLL(LIB_PATH)
+    _lib = declare(C.CDLL(LIB_PATH))
+    return _lib
+
+
+def declare(L: C.CDLL) -> C.CDLL:
+    """Declares the argument and result types of every entry point of a
+    loaded libtransims."""
     vp, i32, u64p = C.c_void_p, C.c_int32, C.POINTER(C.c_uint64)
     L.sim_create.argtypes = [C.POINTER(sim_config), C.POINTER(vp)]
     L.sim_footprint.argtypes = [vp, C.POINTER(sim_params),
@@ -131,7 +137,6 @@ def load_library() -> C.CDLL:
     for name in declared_symbols():
         if name != "sim_last_error":
             getattr(L, name).restype = C.c_int
-    _lib = L
     return L
 
 
