@@ -269,3 +269,39 @@ def test_link_costs_shape_the_tiles(lib, grid):
     rc, t = h.tiling(0)
     assert rc == sim.OK and t.n_tiles > base
     h.close()
+
+
+def test_ring_mode_checks(lib):
+    h = Host(lib)
+    ring = S.ring()
+    assert h.load_network(0, ring) == sim.OK, h.err()
+    assert h.load_vehicles(0, ring) == sim.OK, h.err()
+    assert h.step([0], 10) == sim.OK
+
+    def with_(name, i, val):
+        arr = getattr(ring, name).copy()
+        arr[i] = val
+        return broken(ring, **{name: arr})
+
+    bad = {
+        "cell past the ring": with_("init_x", 3, ring.link_len[0]),
+        "negative cell": with_("init_x", 3, -1),
+        "two vehicles on one cell": with_("init_x", 3, ring.init_x[4]),
+        "speed above vmax": with_("init_v", 3, ring.vmax + 1),
+        "other lane": with_("init_lane", 3, 1),
+        "not on the ring": with_("init_status", 3, S.WAITING),
+        "no placement": broken(ring, init_status=None),
+    }
+    for name, scen in bad.items():
+        assert h.load_network(0, scen, nbytes=1 << 20) == sim.OK, name
+        assert h.load_vehicles(0, scen) == sim.E_INVAL, name
+        assert h.step([0], 1) == sim.E_STATE, name
+    # the ring keeps its vehicles in LDS: at most 4096
+    crowded = S.ring(L=8000, n=4097)
+    assert h.load_network(0, crowded, nbytes=1 << 20) == sim.OK
+    assert h.load_vehicles(0, crowded) == sim.E_CAPACITY
+    # a ring is one single-lane link of 1..32767 cells
+    for kw in ({"link_len": np.array([32768], np.int32)},
+               {"link_lanes": np.array([2], np.int8)}):
+        assert h.load_network(0, broken(ring, **kw), nbytes=1 << 20) == sim.E_INVAL
+    h.close()
