@@ -1,6 +1,9 @@
 """Host-side helpers of bench.py: the kernel-source digest ignores comments,
-kernel kinds map to their families, and the all-cores oracle rate counts
-exactly the updates of the scenarios it ran."""
+kernel kinds map to their families, the all-cores oracle rate counts
+exactly the updates of the scenarios it ran, the roofline object prices
+the algorithmic bytes per launch against the launch time and reports
+measured traffic only where it was measured, and more than one GPU is
+refused."""
 import os
 import sys
 
@@ -42,3 +45,61 @@ def test_all_cores_oracle_counts_every_update():
         assert r["vehicle_updates"] == want
     assert r["value"] > 0 and r["kind"] == "oracle"
     assert {"cpu_model", "nproc", "usable_cores"} <= set(r["host"])
+
+
+def test_more_than_one_gpu_is_refused():
+    import subprocess
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, "bench.py", "--gpus", "2"], cwd=root,
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2 and "one GPU" in r.stderr and r.stdout == ""
+
+
+def test_algorithmic_bytes_split_between_the_kernels():
+    st = {"c_occ": 1000, "veh_updates": 70, "crossings": 5, "exits": 2,
+          "insertions": 3}
+    step = 2 * 1000 + 8 * 70 + 16 * 7 + 8 * 3
+    assert bench.algorithmic_bytes("step", st) == step
+    assert (bench.algorithmic_bytes("front", st) +
+            bench.algorithmic_bytes("back", st)) == step
+    assert bench.algorithmic_bytes("ring", st) == 2 * 1000 + 8 * 70
+
+
+def test_roofline_from_event_time_and_traffic_validity(monkeypatch):
+    st = {"c_occ": 4_000_000, "veh_updates": 100_000, "crossings": 3_000,
+          "exits": 500, "insertions": 600}
+    kt = {"front": (0, 0.0), "back": (0, 0.0), "ring": (0, 0.0),
+          "step": (100, 1.3)}
+    r = bench.roofline_from(kt, [st, st], region_ms=1.2, workload="portland",
+                            steps=3600)
+    per_launch = bench.algorithmic_bytes("step", {k: 2 * v for k, v in st.items()}) / 100
+    assert r["algorithmic_bytes_per_launch"] == per_launch
+    assert r["avg_launch_us"] == 12.0  # the region's time per launch
+    assert r["achieved"] == per_launch / 12e-6 / 1e9
+    assert r["frac"] == r["achieved"] / 8000.0 and r["bound"] == "hbm"
+    # traffic only for the workload, horizon and tiles it was measured on
+    assert r["traffic"] == bench.MEASURED_TRAFFIC[bench.kernel_digest("step")][
+        "portland"][0]["bytes_per_launch"]
+    assert bench.roofline_from(kt, [st], region_ms=1.2, workload="portland",
+                               steps=1800)["traffic"] is None
+    assert bench.roofline_from(kt, [st], region_ms=1.2, workload="portland",
+                               steps=3600, tiles=(8, 1024))["traffic"] is None
+    # and only while the kernel sources are the ones it was measured on
+    monkeypatch.setattr(bench, "kernel_digest", lambda fam="step": "0" * 16)
+    assert bench.roofline_from(kt, [st], region_ms=1.2, workload="portland",
+                               steps=3600)["traffic"] is None
+
+
+def test_roofline_prices_the_two_kernels_together():
+    st = {"c_occ": 10_000, "veh_updates": 900, "crossings": 40, "exits": 4,
+          "insertions": 9}
+    kt = {"front": (50, 2.0), "back": (50, 1.5), "ring": (0, 0.0),
+          "step": (0, 0.0)}
+    r = bench.roofline_from(kt, [st], region_ms=5.0)
+    assert r["kernel"] == "k_front + k_back"
+    assert r["algorithmic_bytes_per_launch"] == bench.algorithmic_bytes("step", st) / 50
+    assert r["avg_launch_us"] == 100.0
+    # without an event time of the region: the dominant kernel alone
+    r = bench.roofline_from(kt, [st])
+    assert r["kernel"] == "k_front" and r["avg_launch_us"] == 40.0
+    assert r["algorithmic_bytes_per_launch"] == bench.algorithmic_bytes("front", st) / 50
