@@ -68,6 +68,11 @@
  *      claim, no trip end) and sees extra = 0, so it stops by the last cell.
  *  S3  While green nothing changes: the unsignalised priority rule of R7
  *      applies among the green approaches of the node.
+ *
+ * Parity unpinned: the lane changes of R6 and the node arbitration of R7
+ * beyond the hand-worked cases and the invariants the tests check.  The
+ * paper prints no worked example or number for them, so on large networks
+ * this code is held to the readings above, not to printed values.
  */
 #include "transims_oracle.h"
 
