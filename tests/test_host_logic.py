@@ -305,3 +305,27 @@ def test_ring_mode_checks(lib):
                {"link_lanes": np.array([2], np.int8)}):
         assert h.load_network(0, broken(ring, **kw), nbytes=1 << 20) == sim.E_INVAL
     h.close()
+
+
+@pytest.mark.parametrize("graph_steps", [0, 16, -1])
+def test_kernel_time_bookkeeping(lib, grid, lc_grid, graph_steps):
+    # profiled steps: graphs of graph_steps steps with event nodes between
+    # the kernels (and a graph of its own for the remainder), or launches
+    # bracketed by events; every launch is counted under its kernel kind
+    h = Host(lib, max_slots=2, graph_steps=graph_steps)
+    assert h.load_network(0, grid) == sim.OK and h.load_vehicles(0, grid) == sim.OK
+    assert h.load_network(1, lc_grid) == sim.OK and h.load_vehicles(1, lc_grid) == sim.OK
+    assert h.lib.sim_profile(h.h, 1) == sim.OK
+    for slots, n in (([0], 70), ([1], 70), ([0, 1], 37)):
+        assert h.step(slots, n) == sim.OK
+    kt = (sim.sim_kernel_time * 4)()
+    assert h.lib.sim_kernel_times(h.h, kt) == sim.OK
+    launches = {name: kt[k].launches
+                for k, name in enumerate(("front", "back", "ring", "step"))}
+    # slot 0 takes one kernel per step, slot 1 two; together, one of each
+    assert launches == {"front": 70 + 37, "back": 70 + 37, "ring": 0,
+                        "step": 70 + 37}
+    # the sums start again after a read
+    assert h.lib.sim_kernel_times(h.h, kt) == sim.OK
+    assert all(kt[k].launches == 0 for k in range(4))
+    h.close()
