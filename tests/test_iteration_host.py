@@ -1,5 +1,6 @@
-"""Host side of the iteration series: link travel times from exit times and
-the re-routing of a fraction of the travellers."""
+"""Host side of the iteration series: link travel times from exit times,
+the re-routing of a fraction of the travellers, and the whole loop with the
+oracle standing in for the GPU context."""
 import numpy as np
 
 from paper_cs_0105004_amd import iteration as I
@@ -44,3 +45,57 @@ def test_reroute_keeps_endpoints_and_connectivity():
                             np.random.Generator(np.random.PCG64(4)))
     assert np.array_equal(ids, ids2)
     assert np.array_equal(again.route_links, new.route_links)
+
+
+def test_series_loop_on_the_oracle(monkeypatch):
+    # the whole loop with the oracle standing in for the GPU context: each
+    # run simulates the current plans, and re-routing changes the plans of
+    # about the stated fraction of travellers and nothing else
+    import torch
+
+    import oracle
+    from paper_cs_0105004_amd import iteration as It
+    from paper_cs_0105004_amd import sim
+
+    class OracleContext:
+        def __init__(self, max_slots=1, **kw):
+            self.o = None
+
+        def load(self, k, scen, link_cost=None):
+            if self.o:
+                self.o.close()
+            self.o = oracle.OracleSim(scen)
+
+        def step(self, k, n):
+            self.o.step(n)
+
+        def stats(self, k):
+            return self.o.stats()
+
+        def state(self, k):
+            return self.o.state()
+
+        def tiling(self, k):
+            return {"e_tile": 1.0}
+
+        def link_costs(self, k):
+            raise AssertionError("no feedback was asked for")
+
+        def close(self):
+            self.o.close()
+
+    monkeypatch.setattr(sim, "Context", OracleContext)
+    monkeypatch.setattr(torch.cuda, "synchronize", lambda *a: None)
+    scen = S.portland_like(scale=0.02, T=300, depart_max=100, seed=4)
+    recs = It.run_series(scen, n_runs=3, frac=0.2, seed=1, feedback=False)
+    assert [r["run"] for r in recs] == [0, 1, 2]
+    for r in recs:
+        o = oracle.OracleSim(r["scenario"])
+        o.step(r["scenario"].T)
+        assert r["hash"] == o.stats()["hash"]
+        o.close()
+    a, b = recs[0]["scenario"], recs[1]["scenario"]
+    changed = sum(not np.array_equal(
+        a.route_links[a.route_off[i]:a.route_off[i + 1]],
+        b.route_links[b.route_off[i]:b.route_off[i + 1]]) for i in range(a.n_veh))
+    assert 0 < changed <= round(0.2 * a.n_veh)
