@@ -4,10 +4,10 @@
 // A step is two kernels, the GPU form of the paper's per-step sequence of a
 // lane-change sub-step and a velocity-and-move sub-step, each followed by a
 // boundary exchange (Section "Micro-simulation parallelization: Domain
-// decomposition"): the kernel boundaries are the two exchanges.  Each workgroup is one wavefront that
-// owns a tile of whole links (at most 64 lanes); a lane's vehicles live in a
-// lead-first ring buffer, so the per-step traffic is proportional to the
-// vehicles, not to the cells.
+// decomposition"): the kernel boundaries are the two exchanges.  Each
+// workgroup is one wavefront that owns a tile of whole links (at most 64
+// lanes); a lane's vehicles live in a lead-first ring buffer, so the
+// per-step traffic is proportional to the vehicles, not to the cells.
 //
 //   k_front  (sub-step 1): merge the vehicle handed over by the upstream
 //            node, let one vehicle per link leave parking, change lanes,

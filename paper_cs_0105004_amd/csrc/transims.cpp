@@ -646,7 +646,8 @@ static sim_status load_vehicles_body(sim_ctx* c, int32_t slot,
       if (v->init_lane[i] != 0 || v->init_x[i] < 0 || v->init_x[i] >= Lr ||
           v->init_v[i] < 0 || v->init_v[i] > vmax)
         return fail(c, SIM_E_INVAL, "vehicle %d: placement out of range", i);
-      if (used[v->init_x[i]]++) return fail(c, SIM_E_INVAL, "two vehicles share cell %d", v->init_x[i]);
+      if (used[v->init_x[i]]++)
+        return fail(c, SIM_E_INVAL, "two vehicles share cell %d", v->init_x[i]);
       idx[i] = i;
     }
     std::sort(idx.begin(), idx.end(),
