@@ -97,7 +97,7 @@ def test_each_planted_mistake_fails_a_hand_case(name, old, new, cases,
 
 
 # Slips elsewhere in the oracle (the ring, the draws, signals, exit times,
-# parking): each mutant must make the rest of the oracle's pins fail.  They
+# parking, the state hash): each mutant must make the rest of the oracle's pins fail.  They
 # run in a child process that loads the mutant through TRANSIMS_ORACLE_LIB.
 RING = "    s->nx[i] = (x + v3) % L;"
 WIDE_MUTANTS = [
@@ -125,13 +125,23 @@ WIDE_MUTANTS = [
     ("red_light_ignored", "if (is_red(s, l, s->t)) continue;", "if (0) continue;"),
     ("exit_time_one_late", "s->exit_t[s->route_off[i] + s->rptr[i]] = t;",
      "s->exit_t[s->route_off[i] + s->rptr[i]] = t + 1;"),
+    ("hash_ignores_route_pointer",
+     "return orc_mix64(h ^ (uint64_t)(uint32_t)rptr);", "return orc_mix64(h);"),
+    ("hash_ignores_speed",
+     "((uint64_t)(uint32_t)v << 8) |", "((uint64_t)0 << 8) |"),
+    ("hash_ignores_link",
+     "((uint64_t)(uint32_t)link << 32);", "((uint64_t)0 << 32);"),
+    ("hash_xor_not_sum",
+     "      h += vehicle_hash(i, st, cur_link(s, i),",
+     "      h ^= vehicle_hash(i, st, cur_link(s, i),"),
     ("parking_into_an_occupied_cell",
      "      if (*c >= 0) continue;\n      *c = i;\n      s->status[i] = ORC_ACTIVE;",
      "      *c = i;\n      s->status[i] = ORC_ACTIVE;"),
 ]
 
-PIN_FILES = ["test_oracle_philox.py", "test_oracle_ring.py",
-             "test_oracle_network.py", "test_oracle_signals.py"]
+PIN_FILES = ["test_oracle_hash.py", "test_oracle_philox.py",
+             "test_oracle_ring.py", "test_oracle_network.py",
+             "test_oracle_signals.py"]
 
 
 @pytest.mark.parametrize("name,old,new", WIDE_MUTANTS,
