@@ -97,7 +97,7 @@ def test_each_planted_mistake_fails_a_hand_case(name, old, new, cases,
 
 
 # Slips elsewhere in the oracle (the ring, the draws, signals, exit times,
-# parking, the state hash): each mutant must make the rest of the oracle's pins fail.  They
+# parking, the state hash, the step counters): each mutant must make the rest of the oracle's pins fail.  They
 # run in a child process that loads the mutant through TRANSIMS_ORACLE_LIB.
 RING = "    s->nx[i] = (x + v3) % L;"
 WIDE_MUTANTS = [
@@ -134,12 +134,22 @@ WIDE_MUTANTS = [
     ("hash_xor_not_sum",
      "      h += vehicle_hash(i, st, cur_link(s, i),",
      "      h ^= vehicle_hash(i, st, cur_link(s, i),"),
+    ("c_occ_counts_empty_lanes",
+     "      if (s->lead_id[q] >= 0) s->st.c_occ += s->len[l];\n"
+     "      else s->rear_x[q] = s->len[l];",
+     "      s->st.c_occ += s->len[l];\n"
+     "      if (s->lead_id[q] < 0) s->rear_x[q] = s->len[l];"),
+    ("crossing_not_counted", "s->st.crossings++;", ";"),
+    ("insertion_not_counted", "s->st.insertions++;", ";"),
+    ("lane_change_counted_twice", "s->st.lane_changes++;", "s->st.lane_changes += 2;"),
+    ("exit_not_counted", "s->st.exits++;", ";"),
     ("parking_into_an_occupied_cell",
      "      if (*c >= 0) continue;\n      *c = i;\n      s->status[i] = ORC_ACTIVE;",
      "      *c = i;\n      s->status[i] = ORC_ACTIVE;"),
 ]
 
-PIN_FILES = ["test_oracle_hash.py", "test_oracle_philox.py",
+PIN_FILES = ["test_oracle_hash.py", "test_oracle_counters.py",
+             "test_oracle_philox.py",
              "test_oracle_ring.py", "test_oracle_network.py",
              "test_oracle_signals.py"]
 
