@@ -1,8 +1,9 @@
 """The seeded input generators against the recipes they stand for: the
 Portland-sized grid's sizes and ranges, strong connectivity, connected
 routes between distinct nodes; the 200k-link recipe's ranges
-(at 1/100 scale); the batch's link-count and demand ranges; the ring; and
-determinism in the seed."""
+(at 1/100 scale); the batch's link-count and demand ranges; the ring;
+determinism in the seed; and the priority ranks and turn-lane ranges of
+reading R9."""
 import numpy as np
 import pytest
 from scipy.sparse import csr_matrix
@@ -98,3 +99,41 @@ def test_generators_are_deterministic_in_the_seed():
               "route_off", "route_links"):
         np.testing.assert_array_equal(getattr(a, f), getattr(b, f))
     assert not np.array_equal(a.route_links, c.route_links)
+
+
+def test_ranks_and_turn_lanes_follow_reading_r9():
+    sc = S.portland_like(scale=0.05, T=100, seed=8,
+                         flags=S.FLAG_LANE_CHANGE | S.FLAG_TURN_LANES)
+    d = sc.node_xy[sc.link_to] - sc.node_xy[sc.link_from]
+    ew = np.abs(d[:, 0]) >= np.abs(d[:, 1])
+    for node in range(sc.n_nodes):
+        into = np.flatnonzero(sc.link_to == node)
+        if len(into) == 0:
+            continue
+        # ranks 0..k-1 once each; more lanes first, then east-west, then id
+        by_rank = into[np.argsort(sc.link_rank[into])]
+        assert sorted(sc.link_rank[into]) == list(range(len(into)))
+        keys = [(-int(sc.link_lanes[l]), not ew[l], int(l)) for l in by_rank]
+        assert keys == sorted(keys)
+    for l in range(sc.n_links):
+        a, b = sc.conn_off[l], sc.conn_off[l + 1]
+        outs = sc.conn_out[a:b]
+        # every movement but the U-turn, each once
+        want = {o for o in np.flatnonzero(sc.link_from == sc.link_to[l])
+                if sc.link_to[o] != sc.link_from[l]}
+        assert set(outs.tolist()) == want and len(outs) == len(want)
+        lo, hi = sc.conn_lo[a:b].astype(int), sc.conn_hi[a:b].astype(int)
+        n = int(sc.link_lanes[l])
+        if len(outs) == 0:
+            continue
+        # left to right: ranges move right, start at lane 0, end at the last
+        # lane, and leave no lane without a movement
+        assert lo[0] == 0 and hi[-1] == n - 1
+        assert (lo <= hi).all() and (np.diff(lo) >= 0).all() and (np.diff(hi) >= 0).all()
+        covered = set()
+        for x, y in zip(lo, hi):
+            covered |= set(range(x, y + 1))
+        assert covered == set(range(n))
+        # turning left means turning toward the left of the arrival direction
+        cross = d[l, 0] * d[outs, 1] - d[l, 1] * d[outs, 0]
+        assert (np.diff(np.sign(np.round(cross, 9))) <= 0).all()
