@@ -329,3 +329,21 @@ def test_kernel_time_bookkeeping(lib, grid, lc_grid, graph_steps):
     assert h.lib.sim_kernel_times(h.h, kt) == sim.OK
     assert all(kt[k].launches == 0 for k in range(4))
     h.close()
+
+
+def test_c_example_builds_and_runs(lib, tmp_path):
+    # the C usage example compiles as plain C11 against the header and runs
+    # every call of its sequence with SIM_OK (against the host-only library)
+    gcc = shutil.which("gcc")
+    if not gcc:
+        pytest.skip("no gcc")
+    libdir = os.path.dirname(lib._name)
+    exe = str(tmp_path / "c_example")
+    subprocess.check_call(
+        [gcc, "-std=c11", "-Wall", "-Werror", "-D__HIP_PLATFORM_AMD__",
+         "-I" + os.path.join(ROOT, "include"), "-I/opt/rocm/include",
+         os.path.join(HERE, "helpers", "c_example.c"),
+         lib._name, "-Wl,-rpath," + libdir, "-o", exe])
+    r = subprocess.run([exe], capture_output=True, text=True, timeout=60)
+    assert r.returncode == 0, r.stderr
+    assert r.stdout.startswith("t 20,")
