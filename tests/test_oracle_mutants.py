@@ -51,6 +51,9 @@ MUTANTS = [
      "s->extra[i] = s->rear_x[tq] + 1 < vmax ? s->rear_x[tq] + 1 : vmax;"),
     ("node_key_lane_before_rank",
      "int32_t key = s->rank[l] * 8 + k;", "int32_t key = k * 8 + s->rank[l];"),
+    ("candidate_range_includes_vmax",  # len-1-x < vmax read as <=
+     "if (i < 0 || s->len[l] - 1 - s->x[i] >= vmax) continue;",
+     "if (i < 0 || s->len[l] - 1 - s->x[i] > vmax) continue;"),
     ("loser_keeps_room",  # every candidate, not only the winner, gets extra
      "} else if (key == s->best[tq]) {", "} else {"),
     ("trip_end_without_extra",
@@ -125,6 +128,9 @@ WIDE_MUTANTS = [
     ("red_light_ignored", "if (is_red(s, l, s->t)) continue;", "if (0) continue;"),
     ("exit_time_one_late", "s->exit_t[s->route_off[i] + s->rptr[i]] = t;",
      "s->exit_t[s->route_off[i] + s->rptr[i]] = t + 1;"),
+    ("lane_change_uses_the_slowdown_draw",
+     "draw(s->p.seed, i, t, 0u) >= s->p.lc_thr",
+     "draw(s->p.seed, i, t, 1u) >= s->p.lc_thr"),
     ("hash_ignores_route_pointer",
      "return orc_mix64(h ^ (uint64_t)(uint32_t)rptr);", "return orc_mix64(h);"),
     ("hash_ignores_speed",

@@ -230,3 +230,24 @@ def test_restart_from_saved_state(small_grid):
     sa, sb = a.state(), b.state()
     for key in sa:
         assert np.array_equal(sa[key], sb[key]), key
+
+
+def test_lane_change_draw_is_sub_step_0():
+    # reading R3: a vehicle that qualifies for a discretionary change takes
+    # it iff word 0 of Philox4x32-10 at counter (id, t, 0, 0) is below
+    # lc_thr (the Philox function itself is pinned to rocRAND's)
+    import dataclasses
+    case = next(c for c in load_cases() if c["name"] == "lc_discretionary_one_side")
+    base = build(case)
+    taken = []
+    for seed in range(1, 65):
+        scen = dataclasses.replace(base, seed=seed, lc_thr=1 << 31)
+        o = oracle.OracleSim(scen)
+        o.step(1)
+        lane = int(o.state()["lane"][0])
+        o.close()
+        u = int(oracle.philox4x32_10(np.array([0, 0, 0, 0], np.uint32),
+                                     np.array([seed, 0], np.uint32))[0])
+        assert lane == (1 if u < (1 << 31) else 0), seed
+        taken.append(lane)
+    assert 0 < sum(taken) < len(taken)  # both outcomes occur
