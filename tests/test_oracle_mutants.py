@@ -35,6 +35,12 @@ MUTANTS = [
      "if (*cell(s, l, m, x) >= 0) continue;", "if (0) continue;"),
     ("ties_go_right",
      "int32_t sides[2] = {k - 1, k + 1};", "int32_t sides[2] = {k + 1, k - 1};"),
+    ("side_gap_capped_at_vmax_plus_1",
+     "for (int32_t c = x + 1; c < s->len[l] && n < s->p.vmax; ++c) {",
+     "for (int32_t c = x + 1; c < s->len[l] && n <= s->p.vmax; ++c) {"),
+    ("link_start_blocks_the_gap_behind",
+     "    if (c >= 0 && *cell(s, l, m, c) >= 0) break;",
+     "    if (c < 0 || *cell(s, l, m, c) >= 0) break;"),
     ("conflict_not_resolved",
      "if (j >= 0 && s->dec[j] == m) s->dec[i] = -1;", "if (0) s->dec[i] = -1;"),
     ("desperation_non_strict",
@@ -149,6 +155,12 @@ WIDE_MUTANTS = [
     ("insertion_not_counted", "s->st.insertions++;", ";"),
     ("lane_change_counted_twice", "s->st.lane_changes++;", "s->st.lane_changes += 2;"),
     ("exit_not_counted", "s->st.exits++;", ";"),
+    ("winner_room_from_the_front_vehicle",
+     "if (s->rear_x[q] < 0 || s->x[i] < s->rear_x[q]) s->rear_x[q] = s->x[i];",
+     "if (s->rear_x[q] < 0 || s->x[i] > s->rear_x[q]) s->rear_x[q] = s->x[i];"),
+    ("parking_queue_by_id_only",
+     "  if (g_depart[i] != g_depart[j]) return g_depart[i] < g_depart[j] ? -1 : 1;\n",
+     ""),
     ("parking_into_an_occupied_cell",
      "      if (*c >= 0) continue;\n      *c = i;\n      s->status[i] = ORC_ACTIVE;",
      "      *c = i;\n      s->status[i] = ORC_ACTIVE;"),
