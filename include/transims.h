@@ -8,13 +8,13 @@
  * (Section "Microsimulation driving logic"): 7.5 m cells holding at most one
  * vehicle, integer speeds 0..vmax cells per step, accelerate / brake to the
  * gap / random slowdown / move (rules i-iii), a lane-change sub-step before
- * the forward move, unsignalised intersections with priority (gap acceptance
- * on the priority street), and vehicles entering from and exiting to parking
- * along precomputed routes.  The update order follows the paper's per-step
- * sequence: lane-change sub-step, boundary exchange, velocity-and-move
- * sub-step, boundary exchange (Section "Micro-simulation parallelization:
- * Domain decomposition"); on one GPU the two boundary exchanges become
- * kernel boundaries plus in-memory handoff slots.
+ * the forward move, unsignalised intersections with priority (the minor
+ * approach yields to the priority link), and vehicles entering from and
+ * exiting to parking along precomputed routes.  The update order follows
+ * the paper's per-step sequence: lane-change sub-step, boundary exchange,
+ * velocity-and-move sub-step, boundary exchange (Section "Micro-simulation
+ * parallelization: Domain decomposition"); on one GPU the two boundary
+ * exchanges become kernel boundaries plus in-memory handoff slots.
  *
  * Rules the paper leaves open are fixed as follows (the same readings bind
  * every implementation that claims to compute this step):
@@ -81,7 +81,10 @@ typedef struct {
                            0 = default (4)                                  */
   int32_t graph_steps;  /* steps per HIP graph replay in sim_step, at most
                            4096; 0 = default (64); < 0 = launch kernels one
-                           by one                                           */
+                           by one.  Steps left after whole replays (or a
+                           call of fewer steps) run as a graph of their own
+                           when there are at least 8 of them; that graph is
+                           kept while later calls leave the same number   */
   int32_t step_mode;    /* 0 = one kernel per step for scenarios without
                            lane changes whose links all have >= 2*vmax
                            cells, two kernels (lane-change / move sub-step)
@@ -178,50 +181,94 @@ typedef struct {
   uint32_t reserved2;
 } sim_stats_t;
 
-/* Creates a context on the current HIP device.  *out receives it.  The
-   configuration is checked before any device call: a field out of its
-   stated range returns SIM_E_INVAL, another abi_version SIM_E_ABI. */
+/* Creates a context on the current HIP device.  *out receives it.
+   Passage: the whole simulated region advanced as one unit per time step
+   (Section "Micro-simulation parallelization: Domain decomposition"; on
+   one GPU the domains become the workgroup tiles of each loaded slot).
+   cfg is read during the call only.  The context owns its host memory and
+   a small device area (scenario descriptors, counter staging); release it
+   with sim_destroy.  The configuration is checked before any device call:
+   a field out of its stated range returns SIM_E_INVAL, another abi_version
+   SIM_E_ABI; on any error *out is NULL. */
 sim_status sim_create(const sim_config* cfg, sim_ctx** out);
 
 /* Bytes of device workspace that sim_load_network + sim_load_vehicles need
-   for this scenario (the caller allocates them, e.g. as a torch tensor). */
+   for this scenario (the caller allocates them, e.g. as a torch tensor).
+   Passage: the state the driving logic updates -- 7.5 m cells of every lane
+   of every link, and the travellers' plans (Sections "Microsimulation
+   driving logic" and "Introduction"); memory is sized per scenario, as the
+   paper sizes each CPU's domain by its share of links (Section "Graph
+   partitioning").  veh may be NULL (network part only).  Inputs are
+   borrowed for the call and checked as in the loaders: SIM_E_INVAL on bad
+   input, SIM_E_CAPACITY if a count exceeds a library limit.  ctx may be
+   NULL (default configuration). */
 sim_status sim_footprint(const sim_ctx* ctx, const sim_params* p,
                          const sim_network* net, const sim_vehicles* veh,
                          uint64_t* bytes);
 
 /* Loads a network into `slot`, tiling its links onto workgroups (orthogonal
    recursive bisection over link midpoints, weighted by cells or by
-   net->link_cost).  dev_ws is device memory owned by the caller that must
+   net->link_cost).  Passage: links of lanes of 7.5 m cells meeting at
+   nodes (Section "Microsimulation driving logic") and their partitioning
+   by orthogonal bisection (Section "Graph partitioning"); links are never
+   split here (one GPU holds every tile).  Every array of net is borrowed
+   for the call and copied; p gives vmax, slow_thr, lc_thr, lc_desp, seed
+   and flags.  dev_ws is device memory owned by the caller that must
    stay valid until sim_unload; the library never frees it.  Any scenario
    previously in the slot is unloaded, also when the call fails. */
 sim_status sim_load_network(sim_ctx* ctx, int32_t slot, const sim_params* p,
                             const sim_network* net, void* dev_ws,
                             uint64_t ws_bytes);
 
-/* Loads vehicles and routes into a slot holding a network.  Synchronises
-   the context stream before returning.  The routes also set the order in
-   which each XCD's tiles are launched: heaviest first by planned load (the
-   routes using a link times its cells), which shortens a launch's tail and
-   leaves every result unchanged.  The input is checked on the host
-   (route_off starts at 0 and rises strictly, routes connect, placements fit)
-   before it is used; on any error the slot holds no vehicles and must be
-   loaded again before it is stepped. */
+/* Loads vehicles and routes into a slot holding a network. Synchronises the
+   context stream before returning. Passage: each traveller's plan, a route
+   through the network fixed before the simulation (Section "Introduction"),
+   executed by entering from parking at the route's first link and exiting to
+   parking at its last (Sections "Microsimulation driving logic" and "Micro-
+   simulation parallelization: Domain decomposition"). The arrays of v are
+   borrowed for the call and copied; an optional initial state restarts a
+   saved run at step v->t0. The routes also set the order in which each XCD's
+   tiles are launched: heaviest first by planned load (the routes using a
+   link times its cells), which shortens a launch's tail and leaves every
+   result unchanged. The input is checked on the host (route_off starts at 0
+   and rises strictly, routes connect, placements fit) before it is used; on
+   any error the slot holds no vehicles and must be loaded again before it is
+   stepped. */
 sim_status sim_load_vehicles(sim_ctx* ctx, int32_t slot,
                              const sim_vehicles* veh);
 
 /* Enqueues n_steps steps of every listed slot on the context stream and
    returns without waiting.  The slots advance together in one launch per
-   sub-step; they never interact. */
+   sub-step; they never interact.  Passage: one step is one second of
+   traffic (Section "Microsimulation driving logic": rules i-iii, lane
+   changing, intersections) in the per-step order lane change, exchange,
+   speed and move, exchange (Section "Micro-simulation parallelization:
+   Domain decomposition"); parking adds no exchange.  slots is borrowed for
+   the call.  Errors (before anything is enqueued): SIM_E_INVAL for an
+   empty or repeated slot list, SIM_E_STATE for a slot without vehicles,
+   SIM_E_CAPACITY when t would overflow, SIM_E_DEVICE for a failed launch.
+   Device-side errors surface in the next sim_stats. */
 sim_status sim_step(sim_ctx* ctx, const int32_t* slots, int32_t n_slots,
                     int32_t n_steps);
 
 /* Waits for the stream and reports the slot's counters and state hash.
-   Returns SIM_E_DEVICE (with out filled) if device error bits are set. */
+   Passage: the inputs of the real-time ratio, simulated seconds over wall
+   time per step (Section "Performance prediction for the TRANSIMS
+   micro-simulation"), and of the per-step load the paper monitors (Section
+   "Adaptive Load Balancing"): steps taken, vehicles moved, crossings.  out
+   is written by the call.  Returns SIM_E_STATE for an unloaded slot and
+   SIM_E_DEVICE (with out filled) if device error bits are set. */
 sim_status sim_stats(sim_ctx* ctx, int32_t slot, sim_stats_t* out);
 
 /* Waits for the stream and copies the per-vehicle state to host arrays of
    n entries (any may be NULL): status, link (-1 unless ACTIVE), lane, x, v,
-   rptr; exit_t receives route_off[n] entries.  The export goes through a
+   rptr; exit_t receives route_off[n] entries.  Passage: the vehicle state
+   of the cellular automaton -- cell, lane and integer speed (Section
+   "Microsimulation driving logic") -- and the step at which each vehicle
+   left each link of its plan, the link travel times the iteration between
+   runs feeds back (Section "Introduction").  Host arrays are owned by the
+   caller.  Errors: SIM_E_STATE for an unloaded slot, SIM_E_DEVICE if a
+   copy fails.  The export goes through a
    temporary device buffer of 15 bytes per vehicle, allocated and freed
    inside the call. */
 sim_status sim_read_state(sim_ctx* ctx, int32_t slot, int8_t* status,
@@ -269,13 +316,20 @@ typedef struct {
 sim_status sim_profile(sim_ctx* ctx, int32_t enable);
 sim_status sim_kernel_times(sim_ctx* ctx, sim_kernel_time out[4]);
 
-/* Forgets the slot (its workspace may then be released by the caller). */
+/* Forgets the slot (its workspace may then be released by the caller).
+   Passage: the end of one run of an iteration series (Section "Adaptive
+   Load Balancing": the next run starts again from the plans).  Waits for
+   the stream first.  SIM_E_INVAL for a slot out of range. */
 sim_status sim_unload(sim_ctx* ctx, int32_t slot);
 
-/* Destroys the context and its library-owned device and host memory. */
+/* Destroys the context and its library-owned device and host memory.
+   No passage of the paper: resource release only.  Waits for the stream;
+   caller workspaces are never freed.  SIM_E_INVAL for NULL. */
 sim_status sim_destroy(sim_ctx* ctx);
 
-/* Text of the last error on this context ("" if none). */
+/* Text of the last error on this context ("" if none); owned by the
+   context, valid until its next call.  No passage of the paper: error
+   reporting only. */
 const char* sim_last_error(const sim_ctx* ctx);
 
 #ifdef __cplusplus

@@ -47,6 +47,7 @@ struct Slot {
   std::vector<int32_t> conn_off, conn_out;  // internal ids (turn lanes)
   std::vector<int8_t> conn_lo, conn_hi;
   std::vector<int2> tiles, ftiles;  // move sub-step / lane-change sub-step
+  std::vector<int4> plans;  // signal plans {cycle, red, offset mod cycle, 0}
   std::vector<double> weight;  // internal order
   std::vector<double> ftile_w;  // summed link weight of each tile
   bool measured = false;        // weights are measured costs (link_cost)
@@ -83,9 +84,13 @@ struct sim_ctx {
   int fused_slot = -1;   // the only fused slot of the work list, or -1
   int single_slot = -1;  // the only two-kernel slot of the work list, or -1
   int n_extra = 0;       // extra move wavefronts of the single slot
-  // a HIP graph of graph_steps steps of the current work list
+  // a HIP graph of graph_steps steps of the current work list, and one of
+  // the last remainder length (a call of fewer steps, or the steps left
+  // after whole replays), reused while calls keep that length
   hipGraphExec_t graph = nullptr;
   int graph_k = 0;
+  hipGraphExec_t rgraph = nullptr;
+  int rgraph_k = 0;
   // kernel timing
   bool profile = false;
   std::vector<hipEvent_t> events;  // pairs around direct launches
@@ -144,6 +149,9 @@ struct NetDims {
 
 constexpr int64_t kExtraRunsMax = 1024;  // extra move wavefronts per step
 constexpr int32_t kMaxGraphSteps = 4096;  // steps per HIP graph
+// a remainder of at least this many steps runs as a cached graph of its
+// own; shorter ones are launched kernel by kernel
+constexpr int32_t kMinRestGraph = 8;
 
 // entries of the list of extra move wavefronts for `tiles` tiles
 int64_t extra_cap(int64_t tiles, int pieces) {
@@ -358,6 +366,7 @@ extern "C" sim_status sim_destroy(sim_ctx* c) {
   if (c->d_work) (void)hipFree(c->d_work);
   if (c->d_list) (void)hipFree(c->d_list);
   if (c->graph) (void)hipGraphExecDestroy(c->graph);
+  if (c->rgraph) (void)hipGraphExecDestroy(c->rgraph);
   delete c;
   return SIM_OK;
 }
@@ -573,7 +582,8 @@ static sim_status load_network_body(sim_ctx* c, int32_t slot,
   HIPCHK(c, up(const_cast<int32_t*>(d.link_ext), S.ext_of.data(), L, s));
   HIPCHK(c, up(const_cast<int4*>(d.lane_info), lane_info.data(), S.n_lanes, s));
   if (d.n_plans > 0) {
-    std::vector<int4> plans(d.n_plans);
+    std::vector<int4>& plans = S.plans;
+    plans.resize(d.n_plans);
     for (int32_t j = 0; j < d.n_plans; ++j)
       plans[j] = make_int4(net->plan_cycle[j], net->plan_red[j],
                            net->plan_offset[j] % net->plan_cycle[j], 0);
@@ -850,6 +860,13 @@ static sim_status load_vehicles_body(sim_ctx* c, int32_t slot,
         const uint32_t meta = (uint32_t)S.lane_info[qq].y;
         const uint32_t xvf = (uint32_t)state[qq].x, ni = (uint32_t)state[qq].y;
         if (lmeta_len(meta) - 1 - xvf_x(xvf) >= vmax || (xvf_fl(xvf) & kFlLast)) continue;
+        // a lead vehicle held by a red light claims nothing in step t0,
+        // as in the kernel that registers the claims of later steps
+        const int pl = lmeta_plan(meta);
+        if (pl >= 0) {
+          const int4 q = S.plans[pl];
+          if ((int)(((uint32_t)v->t0 + (uint32_t)q.z) % (uint32_t)q.x) < q.y) continue;
+        }
         const int k = lmeta_k(meta);
         const int32_t tgt = rinfo_lane0(ni) + std::min(k, rinfo_lanes(ni) - 1);
         cl[tgt] = std::min(cl[tgt], lmeta_rank(meta) * 8 + k);
@@ -932,6 +949,11 @@ sim_status build_work(sim_ctx* c, const std::vector<int32_t>& net,
     (void)hipGraphExecDestroy(c->graph);
     c->graph = nullptr;
     c->graph_k = 0;
+  }
+  if (c->rgraph) {
+    (void)hipGraphExecDestroy(c->rgraph);
+    c->rgraph = nullptr;
+    c->rgraph_k = 0;
   }
   if (c->pgraph) {
     (void)hipGraphExecDestroy(c->pgraph);
@@ -1186,6 +1208,21 @@ static sim_status step_body(sim_ctx* c, const int32_t* slots, int32_t n_slots,
         c->graph_k = K;
       }
       for (; done + K <= n_steps; done += K) HIPCHK(c, hipGraphLaunch(c->graph, c->stream));
+    }
+    if (K > 0 && !c->profile && n_steps - done >= kMinRestGraph) {
+      // the remainder as a graph of its own, kept for the next call that
+      // leaves the same remainder (e.g. repeated windows of a few steps)
+      const int R = n_steps - done;
+      if (!c->rgraph || c->rgraph_k != R) {
+        if (c->rgraph) (void)hipGraphExecDestroy(c->rgraph);
+        c->rgraph = nullptr;
+        c->rgraph_k = 0;
+        st = build_graph(c, R, false, &c->rgraph);
+        if (st != SIM_OK) return st;
+        c->rgraph_k = R;
+      }
+      HIPCHK(c, hipGraphLaunch(c->rgraph, c->stream));
+      done = n_steps;
     }
     const int32_t rest = n_steps - done;
     const int n_fw = c->n_fwork, n_tw = c->n_work - c->n_fwork;

@@ -70,24 +70,28 @@ def test_roofline_from_event_time_and_traffic_validity(monkeypatch):
           "exits": 500, "insertions": 600}
     kt = {"front": (0, 0.0), "back": (0, 0.0), "ring": (0, 0.0),
           "step": (100, 1.3)}
+    table = {bench.kernel_digest("step"): {"portland": [
+        {"window": (1800, 100), "tiles": (0, 0), "bytes_per_launch": 7.5e6}]}}
+    monkeypatch.setattr(bench, "MEASURED_TRAFFIC", table)
     r = bench.roofline_from(kt, [st, st], region_ms=1.2, workload="portland",
-                            steps=3600)
+                            window=(1800, 100))
     per_launch = bench.algorithmic_bytes("step", {k: 2 * v for k, v in st.items()}) / 100
     assert r["algorithmic_bytes_per_launch"] == per_launch
     assert r["avg_launch_us"] == 12.0  # the region's time per launch
     assert r["achieved"] == per_launch / 12e-6 / 1e9
     assert r["frac"] == r["achieved"] / 8000.0 and r["bound"] == "hbm"
-    # traffic only for the workload, horizon and tiles it was measured on
-    assert r["traffic"] == bench.MEASURED_TRAFFIC[bench.kernel_digest("step")][
-        "portland"][0]["bytes_per_launch"]
-    assert bench.roofline_from(kt, [st], region_ms=1.2, workload="portland",
-                               steps=1800)["traffic"] is None
-    assert bench.roofline_from(kt, [st], region_ms=1.2, workload="portland",
-                               steps=3600, tiles=(8, 1024))["traffic"] is None
+    # traffic only for the workload, window and tiles it was measured on
+    assert r["traffic"] == 7.5e6 and "window" in r["traffic_note"]
+    for kw in ({"window": (1800, 20)}, {"window": (1750, 100)},
+               {"window": (1800, 100), "tiles": (8, 1024)},
+               {"window": None}):
+        got = bench.roofline_from(kt, [st], region_ms=1.2,
+                                  workload="portland", **kw)
+        assert got["traffic"] is None and got["traffic_note"].startswith("null")
     # and only while the kernel sources are the ones it was measured on
     monkeypatch.setattr(bench, "kernel_digest", lambda fam="step": "0" * 16)
     assert bench.roofline_from(kt, [st], region_ms=1.2, workload="portland",
-                               steps=3600)["traffic"] is None
+                               window=(1800, 100))["traffic"] is None
 
 
 def test_roofline_prices_the_two_kernels_together():
@@ -103,3 +107,13 @@ def test_roofline_prices_the_two_kernels_together():
     r = bench.roofline_from(kt, [st])
     assert r["kernel"] == "k_front" and r["avg_launch_us"] == 40.0
     assert r["algorithmic_bytes_per_launch"] == bench.algorithmic_bytes("front", st) / 50
+
+
+def test_cpu_window_times_the_window_after_its_own_advance():
+    sc = S.portland_like(scale=0.01, T=200, depart_max=100, seed=4)
+    base, end = bench.cpu_window(sc, 120, 20, budget_s=0.05, max_reps=3)
+    o = oracle.OracleSim(sc)
+    o.step(140)
+    assert end == o.stats()  # counters from t = 0 to the window's end
+    assert base["kind"] == "oracle" and base["cores"] == 1
+    assert base["value"] > 0 and "steps 120..139" in base["sample"]

@@ -7,7 +7,7 @@ import pytest
 import oracle
 from paper_cs_0105004_amd import scenarios as S
 
-from hand_cases import build, check, load_cases
+from hand_cases import BOUNDARIES, build, check, load_cases
 from parity import assert_same_state, assert_same_stats, run_side_by_side
 
 pytestmark = pytest.mark.gpu
@@ -57,12 +57,32 @@ def test_many_rings_in_one_launch(sim):
         assert_same_state(sim.state(k), o.state(), f"ring {k}")
 
 
-@pytest.mark.parametrize("case", load_cases(), ids=lambda c: c["name"])
-def test_hand_worked_cases(sim, case):
+@pytest.fixture(scope="module")
+def sim_two_kernel():
+    from paper_cs_0105004_amd.sim import Context
+    ctx = Context(max_slots=1, step_mode=1)
+    yield ctx
+    ctx.close()
+
+
+# the worked cases and the cases on either side of each comparison of the
+# lane-change and node rules, in both step forms; each is checked against
+# its hand-worked outcome and against the oracle's complete state
+@pytest.mark.parametrize("mode", [0, 1], ids=["one_kernel", "two_kernel"])
+@pytest.mark.parametrize("case", load_cases() + load_cases(BOUNDARIES),
+                         ids=lambda c: c["name"])
+def test_hand_worked_cases(sim, sim_two_kernel, case, mode):
+    ctx = sim if mode == 0 else sim_two_kernel
     scen = build(case)
-    sim.load(0, scen)
-    sim.step(0, case["steps"])
-    check(case, sim.state(0), sim.stats(0))
+    print("case", case["name"], "mode", mode, flush=True)
+    ctx.load(0, scen)
+    ctx.step(0, case["steps"])
+    g, gs = ctx.state(0), ctx.stats(0)
+    check(case, g, gs)
+    o = oracle.OracleSim(scen)
+    o.step(case["steps"])
+    assert_same_stats(gs, o.stats(), case["name"])
+    assert_same_state(g, o.state(), case["name"])
 
 
 @pytest.mark.parametrize("p", ["0", "0.2"])
@@ -202,3 +222,21 @@ def test_one_kernel_step_with_graphs_and_restart():
     a.step(1, 267)
     assert_same_state(a.state(1), o.state(), "restart at t=333")
     a.close()
+
+
+def test_remainder_graphs_reused_and_rebuilt():
+    """Calls of fewer steps than a graph replay run as a cached graph of
+    their own length: repeated windows reuse it, another length rebuilds it,
+    and a remainder below the graph threshold is launched kernel by kernel.
+    Every stretch equals the oracle."""
+    from paper_cs_0105004_amd.sim import Context
+    ctx = Context(max_slots=1, graph_steps=64)
+    scen = S.portland_like(scale=0.02, T=600, depart_max=300, seed=31)
+    ctx.load(0, scen)
+    o = oracle.OracleSim(scen)
+    for n in (20, 20, 20, 30, 5, 64 + 20, 20, 9, 9):
+        ctx.step(0, n)
+        o.step(n)
+        assert_same_stats(ctx.stats(0), o.stats(), f"after a call of {n}")
+    assert_same_state(ctx.state(0), o.state(), "remainder graphs")
+    ctx.close()
