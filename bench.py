@@ -731,6 +731,11 @@ def main():
                     metavar="BYTES", help="only run plain copies of BYTES")
     ap.add_argument("--window", type=float, default=60.0,
                     help="serving: seconds of Poisson arrivals")
+    ap.add_argument("--counter-pass", action="store_true",
+                    help="only the timed window once (fresh load, untimed "
+                         "advance to the demand peak, K steps), for a "
+                         "rocprofv3 counter run: the window's launches are "
+                         "the last K of the step kernels")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not "
@@ -743,11 +748,60 @@ def main():
     torch.cuda.set_device(0)
     if args.copy_calibration > 0:
         return copy_calibration(args.copy_calibration)
+    if args.counter_pass:
+        return counter_pass(args)
     if args.workload == "batched":
         return bench_batched(args)
     if args.workload == "serve":
         return bench_serve(args)
     return bench_single(args)
+
+
+def counter_pass(args):
+    """The timed window of the workload once and nothing after it, so that
+    a profiler's last K dispatches of the step kernels are exactly the
+    window's (no timing, no oracle)."""
+    from paper_cs_0105004_amd import scenarios as S
+    from paper_cs_0105004_amd.sim import Context
+    K = args.steps
+    if args.workload == "batched":
+        scens = S.batched_scenarios()
+        tiles = dict(tile_lanes=args.tile_lanes or 64,
+                     tile_cells=args.tile_cells or 8192,
+                     graph_steps=args.graph_steps or 64)
+    else:
+        scens = [make_workload(args.workload)[0]]
+        tiles = dict(tile_lanes=args.tile_lanes, tile_cells=args.tile_cells)
+    n = len(scens)
+    slots = list(range(n))
+    ctx = Context(max_slots=n, **tiles)
+    for k, sc in enumerate(scens):
+        ctx.load(k, sc)
+    T = scens[0].T
+    best, t_peak, t = -1, 0, 0
+    while t < T:
+        m = min(50, T - t)
+        ctx.step(slots, m)
+        t += m
+        a = sum(ctx.stats(k)["n_active"] for k in slots)
+        if a > best:
+            best, t_peak = a, t
+    t0 = min(max(t_peak, K), T - K)
+    for k, sc in enumerate(scens):
+        ctx.load(k, sc)
+    ctx.step(slots, t0)
+    st_a = [ctx.stats(k) for k in slots]
+    ctx.step(slots, K)
+    st_b = [ctx.stats(k) for k in slots]
+    win = {c: sum(b[c] - a[c] for a, b in zip(st_a, st_b))
+           for c in ("veh_updates", "c_occ", "crossings", "exits",
+                     "insertions")}
+    print(json.dumps({"counter_pass": args.workload, "window": [t0, t0 + K],
+                      "tiles": tiles, "window_counters": win,
+                      "algorithmic_bytes_per_step":
+                          algorithmic_bytes("step", win) / K}), flush=True)
+    ctx.close()
+    return 0
 
 
 def find_peak(ctx, scen, every: int = 50):
