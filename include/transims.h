@@ -251,6 +251,22 @@ sim_status sim_load_vehicles(sim_ctx* ctx, int32_t slot,
 sim_status sim_step(sim_ctx* ctx, const int32_t* slots, int32_t n_slots,
                     int32_t n_steps);
 
+/* sim_step for callers that cannot allocate device memory: code under HIP
+   graph capture, tight serving loops, harnesses that forbid hipMalloc.
+   Same arguments, semantics and results as sim_step, but it calls no
+   hipMalloc, hipFree or other allocating routine and instantiates no
+   graph: the call's work list (one entry per workgroup tile of the listed
+   slots) is copied into a fixed device scratch array of the library, at
+   most 131,072 tiles and 16,384 slots per call (2.1 MiB, held on each GPU
+   the library runs on until the process ends), and every kernel is
+   launched directly on the context stream.  A call beyond those limits
+   returns SIM_E_CAPACITY before enqueuing anything.  Every call on one GPU
+   shares that array: calls on one stream are ordered, but calls that
+   overlap on different streams of the same GPU race and must not be
+   issued.  Host arrays are borrowed for the call. */
+sim_status sim_step_noalloc(sim_ctx* ctx, const int32_t* slots,
+                            int32_t n_slots, int32_t n_steps);
+
 /* Waits for the stream and reports the slot's counters and state hash.
    Passage: the inputs of the real-time ratio, simulated seconds over wall
    time per step (Section "Performance prediction for the TRANSIMS

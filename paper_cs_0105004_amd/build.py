@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libtransims.so")
 SOURCES = ["csrc/transims.cpp", "csrc/tiler.cpp", "csrc/step.hip",
-           "csrc/front_back.hip", "csrc/ring_stats.hip"]
+           "csrc/front_back.hip", "csrc/ring_stats.hip", "csrc/scratch.hip"]
 ARCH = "gfx950"
 
 

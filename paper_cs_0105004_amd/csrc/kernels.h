@@ -52,6 +52,16 @@ hipError_t launch_ring(DevScen* d_descs, const int* d_slots, int n,
 hipError_t launch_stats(const DevScen* d_desc, unsigned long long* d_out,
                         int ring, hipStream_t s);
 
+// The device scratch of sim_step_noalloc (csrc/scratch.hip): at most
+// kScratchWork work items and kScratchSlots listed slots per call.
+constexpr int kScratchWork = 1 << 17;
+constexpr int kScratchSlots = 1 << 14;
+// Looks up the scratch's address on `device`, which must be current; once
+// per device, later calls return at once.
+hipError_t scratch_init(int device);
+// The scratch's device address on `device` (nullptr before scratch_init).
+void* scratch_ptr(int device);
+
 struct ExportBufs {
   int8_t* status;
   int32_t* link;

@@ -101,6 +101,10 @@ struct sim_ctx {
   int pgraph_k = 0;
   std::vector<hipEvent_t> gev;
   std::vector<int> gkind;  // kernel kind of each interval of a profiled graph
+  // the host work plan of the last sim_step_noalloc call, kept until the
+  // next one (its upload reads it)
+  std::vector<int4> nowork;
+  std::vector<int32_t> nolist;
   int64_t acc_launches[4] = {0, 0, 0, 0};
   double acc_ms[4] = {0, 0, 0, 0};
   std::string err;
@@ -345,6 +349,7 @@ static sim_status create_body(const sim_config* cfg, sim_ctx** out) {
     return SIM_E_CAPACITY;
   }
   if (hipGetDevice(&c->device) != hipSuccess ||
+      scratch_init(c->device) != hipSuccess ||
       hipMalloc(&c->d_descs, sizeof(DevScen) * cfg->max_slots) != hipSuccess ||
       hipMalloc(&c->d_stats, sizeof(unsigned long long) * (C_N + 3)) !=
           hipSuccess) {
@@ -889,17 +894,23 @@ static sim_status load_vehicles_body(sim_ctx* c, int32_t slot,
 
 namespace {
 
-sim_status build_work(sim_ctx* c, const std::vector<int32_t>& net,
-                      const std::vector<int32_t>& ring) {
-  std::vector<int32_t> key(net);
-  key.push_back(-1);
-  key.insert(key.end(), ring.begin(), ring.end());
-  if (key == c->work_key) return SIM_OK;
-  // all tiles of all network slots, dealt to the 8 XCDs in contiguous chunks
-  // (workgroup w runs on XCD w mod 8); front tiles first, then back tiles
-  // (fused slots' tiles first: they run in their own kernel)
-  int lc = 0;
+// The work list of one set of slots, computed on the host: all tiles of
+// all network slots, dealt to the 8 XCDs in contiguous chunks (workgroup w
+// runs on XCD w mod 8), fused slots' tiles first (they run in their own
+// kernel), then the tiles of two-kernel slots; and the slot list (network
+// slots, then ring slots).
+struct WorkPlan {
   std::vector<int4> work;
+  std::vector<int32_t> list;
+  int n_fwork = 0, fused_slot = -1, single_slot = -1, n_extra = 0;
+  int lc_words = 0, n_net = 0, n_ring = 0;
+};
+
+void plan_work(const sim_ctx* c, const std::vector<int32_t>& net,
+               const std::vector<int32_t>& ring, WorkPlan& wp) {
+  int lc = 0;
+  std::vector<int4>& work = wp.work;
+  work.clear();
   std::vector<int32_t> fused_slots, two_slots;
   for (int pass = 0; pass < 2; ++pass) {
     std::vector<int2> all;
@@ -940,11 +951,30 @@ sim_status build_work(sim_ctx* c, const std::vector<int32_t>& net,
       const int2 tl = c->slots[dealt[k].x].ftiles[dealt[k].y];
       work.push_back(make_int4(dealt[k].x, tl.x, tl.y, dealt[k].y));
     }
-    if (pass == 0) c->n_fwork = (int)work.size();
+    if (pass == 0) wp.n_fwork = (int)work.size();
   }
-  c->fused_slot = fused_slots.size() == 1 ? fused_slots[0] : -1;
-  c->single_slot = two_slots.size() == 1 ? two_slots[0] : -1;
-  c->n_extra = c->single_slot >= 0 ? c->slots[c->single_slot].d.xcap : 0;
+  wp.fused_slot = fused_slots.size() == 1 ? fused_slots[0] : -1;
+  wp.single_slot = two_slots.size() == 1 ? two_slots[0] : -1;
+  wp.n_extra = wp.single_slot >= 0 ? c->slots[wp.single_slot].d.xcap : 0;
+  wp.list = net;
+  wp.list.insert(wp.list.end(), ring.begin(), ring.end());
+  wp.lc_words = lc;
+  wp.n_net = (int)net.size();
+  wp.n_ring = (int)ring.size();
+}
+
+sim_status build_work(sim_ctx* c, const std::vector<int32_t>& net,
+                      const std::vector<int32_t>& ring) {
+  std::vector<int32_t> key(net);
+  key.push_back(-1);
+  key.insert(key.end(), ring.begin(), ring.end());
+  if (key == c->work_key) return SIM_OK;
+  WorkPlan wp;
+  plan_work(c, net, ring, wp);
+  c->n_fwork = wp.n_fwork;
+  c->fused_slot = wp.fused_slot;
+  c->single_slot = wp.single_slot;
+  c->n_extra = wp.n_extra;
   if (c->graph) {
     (void)hipGraphExecDestroy(c->graph);
     c->graph = nullptr;
@@ -960,14 +990,14 @@ sim_status build_work(sim_ctx* c, const std::vector<int32_t>& net,
     c->pgraph = nullptr;
     c->pgraph_k = 0;
   }
+  const std::vector<int4>& work = wp.work;
+  const std::vector<int32_t>& list = wp.list;
   if (work.size() > c->work_cap) {
     if (c->d_work) HIPCHK(c, hipFree(c->d_work));
     c->d_work = nullptr;
     HIPCHK(c, hipMalloc(&c->d_work, sizeof(int4) * std::max<size_t>(work.size(), 1)));
     c->work_cap = work.size();
   }
-  std::vector<int32_t> list(net);
-  list.insert(list.end(), ring.begin(), ring.end());
   if (list.size() > c->list_cap) {
     if (c->d_list) HIPCHK(c, hipFree(c->d_list));
     c->d_list = nullptr;
@@ -978,9 +1008,9 @@ sim_status build_work(sim_ctx* c, const std::vector<int32_t>& net,
   HIPCHK(c, up(c->d_list, list.data(), (int64_t)list.size(), c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   c->n_work = (int)work.size();
-  c->n_net = (int)net.size();
-  c->n_ring = (int)ring.size();
-  c->lc_words = lc;
+  c->n_net = wp.n_net;
+  c->n_ring = wp.n_ring;
+  c->lc_words = wp.lc_words;
   c->work_key = key;
   return SIM_OK;
 }
@@ -1145,12 +1175,14 @@ extern "C" sim_status sim_kernel_times(sim_ctx* c, sim_kernel_time out[4]) {
   return SIM_OK;
 }
 
-static sim_status step_body(sim_ctx* c, const int32_t* slots, int32_t n_slots,
-                            int32_t n_steps) {
+// The slot list of a step call, checked and split into network and ring
+// slots.
+static sim_status check_step(sim_ctx* c, const int32_t* slots, int32_t n_slots,
+                             int32_t n_steps, std::vector<int32_t>& net,
+                             std::vector<int32_t>& ring) {
   if (!c) return SIM_E_INVAL;
   if (!slots || n_slots < 1) return fail(c, SIM_E_INVAL, "no slots");
   if (n_steps < 0) return fail(c, SIM_E_INVAL, "negative step count");
-  std::vector<int32_t> net, ring;
   std::vector<uint8_t> seen(c->slots.size(), 0);
   for (int32_t k = 0; k < n_slots; ++k) {
     sim_status st = check_slot(c, slots[k]);
@@ -1164,8 +1196,16 @@ static sim_status step_body(sim_ctx* c, const int32_t* slots, int32_t n_slots,
       return fail(c, SIM_E_CAPACITY, "one-kernel steps stop at t = 2^30");
     (S.ring ? ring : net).push_back(slots[k]);
   }
+  return SIM_OK;
+}
+
+static sim_status step_body(sim_ctx* c, const int32_t* slots, int32_t n_slots,
+                            int32_t n_steps) {
+  std::vector<int32_t> net, ring;
+  sim_status st = check_step(c, slots, n_slots, n_steps, net, ring);
+  if (st != SIM_OK) return st;
   if (n_steps == 0) return SIM_OK;
-  sim_status st = build_work(c, net, ring);
+  st = build_work(c, net, ring);
   if (st != SIM_OK) return st;
   if (!net.empty()) {
     const int K = c->cfg.graph_steps;
@@ -1255,6 +1295,55 @@ static sim_status step_body(sim_ctx* c, const int32_t* slots, int32_t n_slots,
     });
     if (st != SIM_OK) return st;
   }
+  for (int32_t sl : net) c->slots[sl].t += n_steps;
+  for (int32_t sl : ring) c->slots[sl].t += n_steps;
+  return SIM_OK;
+}
+
+// sim_step without any allocation: the work list goes to the device's fixed
+// scratch (csrc/scratch.hip) instead of context memory, and every kernel
+// is launched directly (no graph is instantiated).
+static sim_status step_noalloc_body(sim_ctx* c, const int32_t* slots,
+                                    int32_t n_slots, int32_t n_steps) {
+  std::vector<int32_t> net, ring;
+  sim_status st = check_step(c, slots, n_slots, n_steps, net, ring);
+  if (st != SIM_OK) return st;
+  if (n_steps == 0) return SIM_OK;
+  void* base = scratch_ptr(c->device);
+  if (!base) return fail(c, SIM_E_DEVICE, "device scratch not set up");
+  WorkPlan wp;
+  plan_work(c, net, ring, wp);
+  if (wp.work.size() > (size_t)kScratchWork)
+    return fail(c, SIM_E_CAPACITY,
+                "sim_step_noalloc: %zu tiles, the fixed scratch holds %d",
+                wp.work.size(), kScratchWork);
+  if (wp.list.size() > (size_t)kScratchSlots)
+    return fail(c, SIM_E_CAPACITY,
+                "sim_step_noalloc: %zu slots, the fixed scratch holds %d",
+                wp.list.size(), kScratchSlots);
+  c->nowork.swap(wp.work);
+  c->nolist.swap(wp.list);
+  int4* d_work = static_cast<int4*>(base);
+  int* d_list = reinterpret_cast<int*>(d_work + kScratchWork);
+  HIPCHK(c, up(d_work, c->nowork.data(), (int64_t)c->nowork.size(), c->stream));
+  HIPCHK(c, up(d_list, c->nolist.data(), (int64_t)c->nolist.size(), c->stream));
+  const int n_fw = wp.n_fwork, n_tw = (int)c->nowork.size() - wp.n_fwork;
+  if (wp.n_net > 0) {
+    for (int32_t s = 0; s < n_steps; ++s) {
+      if (n_fw > 0)
+        HIPCHK(c, launch_step(c->d_descs, wp.fused_slot, d_work, n_fw, s, c->stream));
+      if (n_tw > 0) {
+        HIPCHK(c, launch_front(c->d_descs, wp.single_slot, d_work + n_fw, n_tw,
+                               c->cfg.back_pieces, s, wp.lc_words, c->stream));
+        HIPCHK(c, launch_back(c->d_descs, wp.single_slot, d_work + n_fw, n_tw,
+                              wp.n_extra, s, c->stream));
+      }
+    }
+    HIPCHK(c, launch_advance(c->d_descs, d_list, wp.n_net, n_steps, c->stream));
+  }
+  if (wp.n_ring > 0)
+    HIPCHK(c, launch_ring(c->d_descs, d_list + wp.n_net, wp.n_ring, n_steps,
+                          c->stream));
   for (int32_t sl : net) c->slots[sl].t += n_steps;
   for (int32_t sl : ring) c->slots[sl].t += n_steps;
   return SIM_OK;
@@ -1449,6 +1538,11 @@ extern "C" sim_status sim_load_vehicles(sim_ctx* c, int32_t slot,
 extern "C" sim_status sim_step(sim_ctx* c, const int32_t* slots, int32_t n_slots,
                                int32_t n_steps) {
   return guarded(c, [&] { return step_body(c, slots, n_slots, n_steps); });
+}
+
+extern "C" sim_status sim_step_noalloc(sim_ctx* c, const int32_t* slots,
+                                       int32_t n_slots, int32_t n_steps) {
+  return guarded(c, [&] { return step_noalloc_body(c, slots, n_slots, n_steps); });
 }
 
 extern "C" sim_status sim_read_state(sim_ctx* c, int32_t slot, int8_t* status,

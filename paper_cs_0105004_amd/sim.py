@@ -124,6 +124,7 @@ def declare(L: C.CDLL) -> C.CDLL:
                                    C.POINTER(sim_network), vp, C.c_uint64]
     L.sim_load_vehicles.argtypes = [vp, i32, C.POINTER(sim_vehicles)]
     L.sim_step.argtypes = [vp, C.POINTER(i32), i32, i32]
+    L.sim_step_noalloc.argtypes = [vp, C.POINTER(i32), i32, i32]
     L.sim_stats.argtypes = [vp, i32, C.POINTER(sim_stats_t)]
     L.sim_read_state.argtypes = [vp, i32] + [vp] * 7
     L.sim_link_costs.argtypes = [vp, i32, vp]
@@ -265,6 +266,15 @@ class Context:
             slots = [slots]
         arr = (C.c_int32 * len(slots))(*slots)
         self._check(self.lib.sim_step(self.h, arr, len(slots), int(n_steps)))
+
+    def step_noalloc(self, slots, n_steps: int = 1):
+        """sim_step_noalloc: the same steps without any device allocation
+        (the work list goes to the library's fixed device scratch)."""
+        if isinstance(slots, int):
+            slots = [slots]
+        arr = (C.c_int32 * len(slots))(*slots)
+        self._check(self.lib.sim_step_noalloc(self.h, arr, len(slots),
+                                              int(n_steps)))
 
     def stats(self, slot: int = 0) -> dict:
         s = sim_stats_t()

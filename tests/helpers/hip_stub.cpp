@@ -130,5 +130,9 @@ hipError_t launch_export(const DevScen*, ExportBufs, int, int, int, int,
                          hipStream_t) {
   return hipSuccess;
 }
+// the allocation-free step's fixed scratch, as a host array
+static int4 stub_scratch[kScratchWork + kScratchSlots / 4];
+hipError_t scratch_init(int) { return hipSuccess; }
+void* scratch_ptr(int) { return stub_scratch; }
 
 }  // namespace tr

@@ -347,3 +347,43 @@ def test_c_example_builds_and_runs(lib, tmp_path):
     r = subprocess.run([exe], capture_output=True, text=True, timeout=60)
     assert r.returncode == 0, r.stderr
     assert r.stdout.startswith("t 20,")
+
+
+def test_step_noalloc_bookkeeping(lib, grid):
+    """The allocation-free step checks its slot list like sim_step, advances
+    the listed slots, and refuses more slots than its fixed scratch holds
+    before enqueuing anything."""
+    h = Host(lib, max_slots=3)
+
+    def noalloc(slots, n):
+        arr = (C.c_int32 * len(slots))(*slots)
+        return lib.sim_step_noalloc(h.h, arr, len(slots), n)
+
+    assert noalloc([0], 1) == sim.E_STATE
+    assert h.load_network(0, grid) == sim.OK
+    assert h.load_vehicles(0, grid) == sim.OK
+    assert noalloc([0], 5) == sim.OK
+    assert noalloc([0, 0], 1) == sim.E_INVAL
+    assert noalloc([0], -1) == sim.E_INVAL
+    assert noalloc([3], 1) == sim.E_INVAL
+    st = sim.sim_stats_t()
+    assert lib.sim_stats(h.h, 0, C.byref(st)) == sim.OK and st.t == 5
+    h.close()
+    # one more ring slot than the scratch's slot list holds
+    n = (1 << 14) + 1
+    h = Host(lib, max_slots=n)
+    ring = S.ring(2, 1, 1, "0", seed=1)
+    inp = sim._Inputs(ring)
+    ws = np.zeros(h.footprint(ring) * n + 256 * n, np.uint8)
+    base = (ws.ctypes.data + 255) // 256 * 256
+    per = (h.footprint(ring) + 255) // 256 * 256
+    for k in range(n):
+        assert lib.sim_load_network(h.h, k, C.byref(inp.params),
+                                    C.byref(inp.net),
+                                    C.c_void_p(base + k * per), per) == sim.OK
+        assert lib.sim_load_vehicles(h.h, k, C.byref(inp.veh)) == sim.OK
+    assert noalloc(list(range(n)), 1) == sim.E_CAPACITY
+    assert "scratch" in h.err()
+    assert lib.sim_stats(h.h, 0, C.byref(st)) == sim.OK and st.t == 0
+    assert noalloc(list(range(n - 1)), 1) == sim.OK
+    h.close()
