@@ -34,8 +34,13 @@
  *     end of the last link (extra = vmax).
  * Every step is integer; results are bit-identical to the CPU oracle.
  *
- * Threading: one context per host thread.  All device work of a context runs
- * on the stream given at creation.  No exception crosses this boundary.
+ * Threading: a context is driven by one host thread.  The one exception is
+ * loading: sim_load_network and sim_load_vehicles may run on other threads
+ * at the same time as the driving thread's calls, for slots that no
+ * concurrent call names (a serving loop loads new scenarios while the slots
+ * already running keep stepping).  A load makes the context's device
+ * current on its thread.  All device work of a context runs on the stream
+ * given at creation.  No exception crosses this boundary.
  */
 #ifndef TRANSIMS_H
 #define TRANSIMS_H
@@ -88,8 +93,11 @@ typedef struct {
   int32_t step_mode;    /* 0 = one kernel per step for scenarios without
                            lane changes whose links all have >= 2*vmax
                            cells, two kernels (lane-change / move sub-step)
-                           otherwise; 1 = always two kernels.  Results are
-                           the same either way.                             */
+                           otherwise; 1 = always two kernels; 2 = as 0, and
+                           the one-kernel step skips lanes that are empty and
+                           stay empty (less memory traffic, one more round of
+                           dependent loads).  Results are the same in every
+                           mode.                                            */
   int32_t tile_cells;   /* one-kernel step, and scenarios with lane
                            changes: a tile also stops at this many cells
                            (len x lanes; a longer link is a tile of its

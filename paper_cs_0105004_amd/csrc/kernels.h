@@ -24,14 +24,17 @@ hipError_t launch_front(const DevScen* d_descs, int slot, const int4* d_work,
 hipError_t launch_back(const DevScen* d_descs, int slot, const int4* d_work,
                        int n_work, int n_extra, int step, hipStream_t s);
 // One kernel for the whole step, for slots whose state is kept by step
-// parity (DevScen::fused); work items as above, one wavefront each.
+// parity (DevScen::fused); work items as above, one wavefront each.  With
+// skip, lanes that are empty and stay empty are neither read nor written
+// (worth it when many more tiles than fit on the device at once share the
+// launch); results are the same either way.
 hipError_t launch_step(const DevScen* d_descs, int slot, const int4* d_work,
-                       int n_work, int step, hipStream_t s);
+                       int n_work, int step, bool skip, hipStream_t s);
 // Host stubs of the step kernels, for building HIP graphs:
-//   step(descs, slot, work, step),
+//   step(descs, slot, work, step) (step_kernel(batched, skip)),
 //   front(descs, slot, work, pieces, step), back(descs, slot, work, n_work,
 //   step), advance(descs, slots, n, k)
-void* step_kernel(bool batched);
+void* step_kernel(bool batched, bool skip);
 void* front_kernel(bool batched);
 void* back_kernel(bool batched);
 void* advance_kernel();

@@ -144,6 +144,17 @@ struct DevScen {
   // fixed-time signal plans {cycle, red, offset, 0}: red at step t iff
   // (t + offset) % cycle < red
   const int4* plans;
+  // one-kernel step, per tile and step parity: tile_live bit i = lane i of
+  // the tile held a vehicle at the start of this step or of the step before
+  // (so both parity buffers of a lane outside the mask hold its empty
+  // state); tile_wake = the step from which the tile must look at every
+  // lane (a parking-queue head may leave, or a queue moved on in the step
+  // before).  arr_bits[parity][lane / 64]: bit set when a vehicle was handed
+  // over into the lane in a step of that parity; cleared by the lane's
+  // tile when it merges the vehicle.
+  unsigned long long* tile_live;
+  int32_t* tile_wake;
+  unsigned long long* arr_bits;
   // arrival handoff per target lane: hand_a {tag = t, xvf, id, rp}, hand_b
   // ninfo
   int4* hand_a;

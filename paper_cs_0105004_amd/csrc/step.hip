@@ -25,6 +25,13 @@ struct StepCtx {
   uint32_t key0, key1;
   uint64_t slow_thr;
 };
+// Addresses only a vehicle crossing a node uses.  They wait in LDS, which
+// keeps them out of the scalar registers through the move.
+struct CrossPtrs {
+  const uint32_t* route_info;
+  int32_t* exit_t;
+  unsigned long long* arr_out;  // arrival bits written this step
+};
 
 __device__ __forceinline__ void step_load(
     StepGroup& G, int g0, int i, int total, int nl, const int* s_pre,
@@ -60,8 +67,7 @@ __device__ __forceinline__ void step_run(
     const int* s_pre, const int* s_extra, const int* s_tgt,
     const uint2 (*s_nhot)[2], const int2 (*s_ncold)[2], int4* s_ends,
     int2* s_second, int* s_left, GAS v2u* hot, GAS uint32_t* hot_w,
-    GAS v2i* cold, const GAS uint32_t* __restrict__ route_info,
-    GAS int32_t* __restrict__ exit_t, GAS v4i* __restrict__ ha_out,
+    GAS v2i* cold, const CrossPtrs* s_xp, GAS v4i* __restrict__ ha_out,
     GAS int32_t* __restrict__ hb_out, GAS int32_t* __restrict__ ht_out,
     unsigned long long& sumv, unsigned long long& cross,
     unsigned long long& exits) {
@@ -95,7 +101,7 @@ __device__ __forceinline__ void step_run(
       if (j >= c0l) {  // an arrival: its whole record
         hot[G.sl[c]] = (v2u){nw, hw.y};
         cold[G.sl[c]] = cw;
-      } else {
+      } else if (nw != hw.x) {  // a vehicle that stays put keeps its word
         hot_w[2 * G.sl[c]] = nw;
       }
       const int lcnt = s_pre[li + 1] - s_pre[li];
@@ -108,17 +114,19 @@ __device__ __forceinline__ void step_run(
       if (j == lcnt - 1) s_ends[li].z = (int)nw;
     } else {  // only a lead vehicle of the previous step passes the node
       const int rp = cw.x;
-      exit_t[rp] = cx.t;
+      const CrossPtrs xp = *s_xp;
+      gp(xp.exit_t)[rp] = cx.t;
       s_left[li] = 1;
       if (fl & kFlLast) {
         ++exits;
       } else {
         const uint32_t nfl = rinfo_flags((uint32_t)cw.y);
         const int tg = s_tgt[li];
-        hb_out[tg] = (nfl & kFlLast) ? 0 : (int)route_info[rp + 2];
+        hb_out[tg] = (nfl & kFlLast) ? 0 : (int)gp(xp.route_info)[rp + 2];
         ha_out[tg] = (v4i){cx.t, (int)pack_xvf(nx - llen, v3, nfl),
                            (int)hw.y, rp + 1};
         ht_out[tg] = (cx.t << 1) | (nx == llen ? 1 : 0);
+        atomicOr(&xp.arr_out[tg >> 6], 1ull << (tg & 63));
         ++cross;
       }
     }
@@ -139,7 +147,7 @@ __device__ __forceinline__ void step_run(
 //   3. moves every vehicle (second sub-step), rear first, 64 at a time;
 //   4. writes the lanes' state for the next step and registers the claims
 //      of the lanes' new lead vehicles for the next step.
-template <bool kBatched>
+template <bool kBatched, bool kSkip>
 __global__ __launch_bounds__(kWave) void k_step(
     const DevScen* __restrict__ descs, int slot, const int4* __restrict__ work,
     int step) {
@@ -152,6 +160,8 @@ __global__ __launch_bounds__(kWave) void k_step(
   __shared__ uint2 s_nhot[kMaxTileLanes][2];  // arrivals of this step
   __shared__ int2 s_ncold[kMaxTileLanes][2];
   __shared__ int4 s_plans[kMaxPlans];
+  __shared__ CrossPtrs s_xp;
+  __shared__ int s_wake;  // the tile's wake step (kSkip)
   const long long c0 = wall_clock64();
   const int4 w = work[blockIdx.x];
   const DevScen& S = descs[kBatched ? w.x : slot];
@@ -182,46 +192,83 @@ __global__ __launch_bounds__(kWave) void k_step(
   GAS v2u* hot = gpv<v2u>(S.hot);
   GAS uint32_t* hot_w = gpv<uint32_t>(S.hot);
   GAS v2i* cold = gpv<v2i>(S.cold);
-  const GAS uint32_t* __restrict__ route_info = gp(S.route_info);
-  GAS int32_t* __restrict__ exit_t = gp(S.exit_t);
   const int i = threadIdx.x;
   const int nl = w.z;
   const bool act = i < nl;
   const int g = w.y + i;
 
-  // 1. what every lane needs from the previous step, in one round: its
-  // static word, its state, the tag of the last handoff into it and (lane
-  // 0) the departure time of its link's queue head
-  // (threads past the tile's lanes read its first lane and drop it, so
-  // that no load waits behind a branch)
-  const int gg = act ? g : w.y;
-  v2i bm = lane_bm[gg];
-  v4i st = ls_cur[gg];
-  int htag = ht_in[gg], qn = qn_cur[gg];
-  if (!act) {
-    bm = (v2i){0, 0};
-    st = (v4i){0, 0, 0, 0};
-    htag = kTagNone;
-    qn = INT32_MAX;
+  // 0. which lanes have anything to do (kSkip): those that held a vehicle
+  // at the start of this step or of the one before (the tile's mask), those
+  // a vehicle was handed over into (the arrival bits), and every lane when
+  // a parking-queue head of the tile may leave (the tile's wake step).  A
+  // lane outside these is empty and stays empty, and both of its parity
+  // buffers already hold that state, so it is neither read nor written.
+  // Without kSkip every lane is looked at; both forms keep the masks, wake
+  // steps and arrival bits up to date, so that either may follow the other.
+  const long long nft = S.n_ftiles;
+  unsigned long long* arr_in = S.arr_bits + (p ^ 1) * ((Q + 63) >> 6);
+  if (threadIdx.x == 0)
+    s_xp = CrossPtrs{S.route_info, S.exit_t, S.arr_bits + p * ((Q + 63) >> 6)};
+  bool full = true, arrb = false, live = act;
+  if (kSkip) {
+    const unsigned long long own = S.tile_live[p * nft + w.w];
+    const int wake = S.tile_wake[p * nft + w.w];
+    if (threadIdx.x == 0) s_wake = wake;
+    full = wake <= t;
+    arrb = act && ((arr_in[(act ? g : w.y) >> 6] >> (g & 63)) & 1ull) != 0;
+    live = act && (full || ((own >> i) & 1ull) != 0 || arrb);
+  }
+  // 1. what every live lane needs from the previous step, in one round:
+  // its static word, its state, the tag of the last handoff into it and the
+  // departure time of its link's queue head
+  v2i bm = {0, 0};
+  v4i st = {0, 0, 0, 0};
+  int htag = kTagNone, qn = INT32_MAX;
+  if (kSkip) {
+    if (live) {
+      bm = lane_bm[g];
+      st = ls_cur[g];
+      qn = qn_cur[g];
+      if (arrb) htag = ht_in[g];
+    }
+  } else {
+    // (threads past the tile's lanes read its first lane and drop it, so
+    // that no load waits behind a branch)
+    const int gg = act ? g : w.y;
+    bm = lane_bm[gg];
+    st = ls_cur[gg];
+    htag = ht_in[gg];
+    qn = qn_cur[gg];
+    if (!act) {
+      bm = (v2i){0, 0};
+      st = (v4i){0, 0, 0, 0};
+      htag = kTagNone;
+      qn = INT32_MAX;
+    }
   }
   load_plans(S, s_plans);
   const uint32_t meta = (uint32_t)bm.y;
-  const int len = act ? lmeta_len(meta) : 1;
+  // (links of a one-kernel slot have at least 2 vmax cells, so len > 1
+  // marks a live lane from here on)
+  const int len = live ? lmeta_len(meta) : 1;
   const int k = lmeta_k(meta), lanes = lmeta_lanes(meta);
   const int key = lmeta_rank(meta) * 8 + k;
   const int head = hc_head(st.w);
-  const int cnt = act ? hc_cnt(st.w) : 0;
+  const int cnt = live ? hc_cnt(st.w) : 0;
   const uint32_t lead_w = (uint32_t)st.x;
   // a vehicle handed over in the previous step joins at the rear (its
   // record is read below); the tag says whether it landed on cell 0
   bool arr = false;
-  if (act && (htag >> 1) == t - 1) {
+  if (live && (htag >> 1) == t - 1) {
     if (cnt >= len) atomicOr(S.err, SIM_DEVERR_LANE_FULL);
     else arr = true;
   }
+  // the arrival bit is consumed: this parity's bits are set again by the
+  // handoffs of the next step but one
+  if (arr) atomicAnd(&arr_in[g >> 6], ~(1ull << (g & 63)));
   const int rear_x =
       arr ? ((htag & 1) ? 0 : 1) : (cnt > 0 ? xvf_x((uint32_t)st.z) : 1);
-  const bool empty0 = act && rear_x != 0;
+  const bool empty0 = len > 1 && rear_x != 0;
   const unsigned long long free0 = __ballot(empty0);
   const int l0 = i - k;  // this link's lane 0 in the tile
   const int qn0 = __shfl(qn, l0);
@@ -254,7 +301,7 @@ __global__ __launch_bounds__(kWave) void k_step(
   // the winner)
   // (a red light holds it back: no claim, no trip end)
   wave_lds_sync();  // the plans in LDS
-  const bool cand = act && cnt > 0 && len - 1 - xvf_x(lead_w) < vmax &&
+  const bool cand = cnt > 0 && len - 1 - xvf_x(lead_w) < vmax &&
                     !sig_red(s_plans, meta, t);
   const bool exits_here = cand && (xvf_fl(lead_w) & kFlLast);
   int tgt = exits_here ? -2 : -1, tm = 0, tlanes = 1, tl0 = 0;
@@ -282,7 +329,7 @@ __global__ __launch_bounds__(kWave) void k_step(
       tpend[m] = th.x == t - 1 ? th.y : kTagNone;
     }
   }
-  if (act) {
+  if (act) {  // (a lane that is not live holds no vehicle)
     s_base[i] = bm.x;
     s_hp[i] = hc_make(head, 0, 0);
     s_len[i] = len;
@@ -335,7 +382,7 @@ __global__ __launch_bounds__(kWave) void k_step(
       if (link_ins && qh + 1 < qend) nrec = wait_rec[qh + 1];
       // winners: extra cells past the link end (rule R7); the claim is
       // cleared for the next use of this buffer
-      if (act) {
+      if (len > 1) {
         int extra = exits_here ? vmax : 0;
         if (tgt >= 0 && claim == key) {
           cl_cur[tgt] = INT32_MAX;
@@ -358,13 +405,21 @@ __global__ __launch_bounds__(kWave) void k_step(
       wave_lds_sync();
     }
     step_run(G, cx, s_len, s_cnt0, s_pre, s_extra, s_tgt, s_nhot, s_ncold,
-             s_ends, s_second, s_left, hot, hot_w, cold, route_info, exit_t,
-             ha_out, hb_out, ht_out, sumv, cross, exits);
+             s_ends, s_second, s_left, hot, hot_w, cold, &s_xp, ha_out,
+             hb_out, ht_out, sumv, cross, exits);
   }
   wave_lds_sync();
 
-  // 4. the lanes for the next step, and the claims of their new leads
-  if (act) {
+  // 4. the lanes for the next step, and the claims of their new leads;
+  // with them the tile's control words for the next step: the lanes that
+  // hold a vehicle now or did at its start, and the wake step -- unchanged
+  // unless this step looked at every lane, which gives the earliest
+  // departure of a queue head (or the next step itself if a queue moved
+  // on, so that the next step copies the new head's departure into the
+  // other parity buffer)
+  bool held = false;
+  int qnx = INT32_MAX;
+  if (len > 1) {
     int4 e = s_ends[i];
     int h1 = head, c1 = cntn;
     if (s_left[i]) {
@@ -375,6 +430,7 @@ __global__ __launch_bounds__(kWave) void k_step(
       e.y = sec.y;
     }
     ls_nxt[g] = (v4i){e.x, e.y, e.z, hc_make(h1, 0, c1)};
+    held = c1 > 0 || s_cnt0[i] > 0;
     if (c1 > 0 && len - 1 - xvf_x((uint32_t)e.x) < vmax &&
         !(xvf_fl((uint32_t)e.x) & kFlLast) && !sig_red(s_plans, meta, t + 1)) {
       const uint32_t ni = (uint32_t)e.y;
@@ -382,21 +438,31 @@ __global__ __launch_bounds__(kWave) void k_step(
                 key);
     }
     if (k == 0) {
+      qnx = qn;
       if (link_ins) {
         lane_qhead[g] = qh + 1;
         lane_qrec[g] = nrec;
-        qn_nxt[g] = qh + 1 < qend ? (nrec.y & ((1 << kDepartBits) - 1))
-                                  : INT32_MAX;
-      } else {
-        qn_nxt[g] = qn;
+        qnx = qh + 1 < qend ? (nrec.y & ((1 << kDepartBits) - 1)) : INT32_MAX;
       }
+      qn_nxt[g] = qnx;
     }
   }
+  const unsigned long long own1 = __ballot(held);
   sumv = wave_sum(sumv);
   cross = wave_sum(cross);
   exits = wave_sum(exits);
   const unsigned long long n_ins = wave_sum((unsigned long long)ins);
+  int wake1;
+  if (kSkip && s_wake > t) {
+    wake1 = s_wake;
+  } else {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) qnx = min(qnx, __shfl_xor(qnx, off));
+    wake1 = n_ins ? min(qnx, t + 1) : qnx;
+  }
   if (i == 0) {
+    S.tile_live[(p ^ 1) * nft + w.w] = own1;
+    S.tile_wake[(p ^ 1) * nft + w.w] = wake1;
     GAS unsigned long long* ctr =
         (GAS unsigned long long*)gp(S.tile_ctr + (long long)w.y * C_N);
     atomicAdd((unsigned long long*)&ctr[C_UPDATES], (unsigned long long)total);
@@ -413,21 +479,34 @@ __global__ __launch_bounds__(kWave) void k_step(
 // ---- launchers -------------------------------------------------------------
 
 hipError_t launch_step(const DevScen* d_descs, int slot, const int4* d_work,
-                       int n_work, int step, hipStream_t s) {
+                       int n_work, int step, bool skip, hipStream_t s) {
   if (n_work <= 0) return hipSuccess;
   (void)hipGetLastError();
-  if (slot < 0)
-    hipLaunchKernelGGL(k_step<true>, dim3(n_work), dim3(kWave), 0, s, d_descs,
-                       0, d_work, step);
-  else
-    hipLaunchKernelGGL(k_step<false>, dim3(n_work), dim3(kWave), 0, s,
-                       d_descs, slot, d_work, step);
+  const dim3 grid(n_work), block(kWave);
+  if (slot < 0) {
+    if (skip)
+      hipLaunchKernelGGL((k_step<true, true>), grid, block, 0, s, d_descs, 0,
+                         d_work, step);
+    else
+      hipLaunchKernelGGL((k_step<true, false>), grid, block, 0, s, d_descs, 0,
+                         d_work, step);
+  } else {
+    if (skip)
+      hipLaunchKernelGGL((k_step<false, true>), grid, block, 0, s, d_descs,
+                         slot, d_work, step);
+    else
+      hipLaunchKernelGGL((k_step<false, false>), grid, block, 0, s, d_descs,
+                         slot, d_work, step);
+  }
   return hipGetLastError();
 }
 
-void* step_kernel(bool batched) {
-  return batched ? reinterpret_cast<void*>(&k_step<true>)
-                 : reinterpret_cast<void*>(&k_step<false>);
+void* step_kernel(bool batched, bool skip) {
+  if (batched)
+    return skip ? reinterpret_cast<void*>(&k_step<true, true>)
+                : reinterpret_cast<void*>(&k_step<true, false>);
+  return skip ? reinterpret_cast<void*>(&k_step<false, true>)
+              : reinterpret_cast<void*>(&k_step<false, false>);
 }
 
 }  // namespace tr

@@ -10,9 +10,13 @@
 #include <cstdio>
 #include <cstring>
 #include <exception>
+#include <map>
+#include <memory>
+#include <mutex>
 #include <new>
 #include <numeric>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "kernels.h"
@@ -76,7 +80,11 @@ struct sim_ctx {
   int* d_list = nullptr;  // network slots, then ring slots
   size_t list_cap = 0;
   unsigned long long* d_stats = nullptr;
-  std::vector<int32_t> work_key;
+  // the (slot, load generation) pairs the work list was built for; a
+  // slot's generation changes with every load and unload, so a work list
+  // is never reused for a slot whose contents changed
+  std::vector<int64_t> work_key;
+  std::vector<uint32_t> slot_gen;
   int n_work = 0, n_net = 0, n_ring = 0, lc_words = 0;
   // the work list holds the tiles of fused slots first (n_fwork items, one
   // kernel per step), then those of two-kernel slots
@@ -107,7 +115,10 @@ struct sim_ctx {
   std::vector<int32_t> nolist;
   int64_t acc_launches[4] = {0, 0, 0, 0};
   double acc_ms[4] = {0, 0, 0, 0};
-  std::string err;
+  // last error text of each calling thread (loads may run on other
+  // threads than the one that steps)
+  std::mutex err_mu;
+  std::map<std::thread::id, std::string> err;
 };
 
 namespace {
@@ -118,7 +129,10 @@ sim_status fail(sim_ctx* c, sim_status st, const char* fmt, ...) {
   va_start(ap, fmt);
   vsnprintf(buf, sizeof buf, fmt, ap);
   va_end(ap);
-  if (c) c->err = buf;
+  if (c) {
+    std::lock_guard<std::mutex> lk(c->err_mu);
+    c->err[std::this_thread::get_id()] = buf;
+  }
   return st;
 }
 
@@ -174,6 +188,9 @@ void carve_network(Carve& cv, const NetDims& nd, DevScen& d, bool ring) {
   d.hand_b = cv.take<int32_t>(2 * Q);
   d.qnext = cv.take<int32_t>(2 * Q);
   d.lane_bm = cv.take<int2>(Q);
+  d.tile_live = cv.take<unsigned long long>(2 * Q);  // at most one tile per lane
+  d.tile_wake = cv.take<int32_t>(2 * Q);
+  d.arr_bits = cv.take<unsigned long long>(2 * ((Q + 63) / 64));
   d.plans = cv.take<int4>(kMaxPlans);
   d.lane_qend = cv.take<int32_t>(Q);
   d.hand_tag = cv.take<int32_t>(2 * Q);
@@ -314,6 +331,40 @@ sim_status check_route_off(sim_ctx* c, int32_t n, const int64_t* route_off) {
   return SIM_OK;
 }
 
+// With step_mode 2 the one-kernel step skips lanes that are empty and stay
+// empty: less memory traffic for one more dependent round of loads per
+// tile, which measured no faster on the Portland-sized network (13.9 vs
+// 13.3 us per step at its demand peak) nor on 64 batched replications
+// (49.3 vs 48.5 us), so the default reads every lane.
+bool skip_lanes(const sim_ctx* c, int /*n_fwork*/) {
+  return c->cfg.step_mode == 2;
+}
+
+// Host threads for encoding `work` route entries: one per 2^20 entries, at
+// most 16 (the host share of one GPU) and at most the machine's threads.
+int host_workers(int64_t work) {
+  const int64_t hw = std::max<int64_t>(1, std::thread::hardware_concurrency());
+  return (int)std::max<int64_t>(
+      1, std::min<int64_t>({16, hw, work >> 20}));
+}
+
+// Calls fn(lo, hi, worker) on `workers` contiguous ranges of [0, n), each
+// on a thread of its own (the calling thread takes range 0).
+template <class F>
+void parallel_ranges(int32_t n, int workers, F&& fn) {
+  if (workers <= 1) {
+    fn(0, n, 0);
+    return;
+  }
+  std::vector<std::thread> th;
+  th.reserve(workers - 1);
+  auto lo = [&](int w) { return (int32_t)((int64_t)n * w / workers); };
+  for (int w = 1; w < workers; ++w)
+    th.emplace_back([&, w] { fn(lo(w), lo(w + 1), w); });
+  fn(lo(0), lo(1), 0);
+  for (std::thread& t : th) t.join();
+}
+
 template <class T>
 hipError_t up(T* dst, const T* src, int64_t n, hipStream_t s) {
   if (n <= 0) return hipSuccess;
@@ -331,7 +382,7 @@ static sim_status create_body(const sim_config* cfg, sim_ctx** out) {
   if (cfg->max_slots < 1 || cfg->max_slots > 65536) return SIM_E_INVAL;
   if (cfg->tile_lanes < 0 || cfg->tile_lanes > kMaxTileLanes) return SIM_E_INVAL;
   if (cfg->back_pieces < 0 || cfg->back_pieces > 8) return SIM_E_INVAL;
-  if (cfg->step_mode < 0 || cfg->step_mode > 1) return SIM_E_INVAL;
+  if (cfg->step_mode < 0 || cfg->step_mode > 2) return SIM_E_INVAL;
   if (cfg->graph_steps > kMaxGraphSteps) return SIM_E_INVAL;
   if (cfg->tile_cells != 0 && (cfg->tile_cells < 64 || cfg->tile_cells > 65536))
     return SIM_E_INVAL;
@@ -344,6 +395,7 @@ static sim_status create_body(const sim_config* cfg, sim_ctx** out) {
   c->stream = reinterpret_cast<hipStream_t>(cfg->stream);
   try {
     c->slots.resize(cfg->max_slots);
+    c->slot_gen.assign(cfg->max_slots, 0u);
   } catch (const std::bad_alloc&) {
     delete c;
     return SIM_E_CAPACITY;
@@ -377,7 +429,10 @@ extern "C" sim_status sim_destroy(sim_ctx* c) {
 }
 
 extern "C" const char* sim_last_error(const sim_ctx* c) {
-  return c ? c->err.c_str() : "no context";
+  if (!c) return "no context";
+  sim_ctx* m = const_cast<sim_ctx*>(c);
+  std::lock_guard<std::mutex> lk(m->err_mu);
+  return m->err[std::this_thread::get_id()].c_str();
 }
 
 static sim_status footprint_body(const sim_ctx* cc, const sim_params* p,
@@ -402,18 +457,28 @@ static sim_status footprint_body(const sim_ctx* cc, const sim_params* p,
   return SIM_OK;
 }
 
+// Loads may run on another host thread than the one that steps: make the
+// context's device current on the calling thread.
+static sim_status use_device(sim_ctx* c) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev != c->device)
+    HIPCHK(c, hipSetDevice(c->device));
+  return SIM_OK;
+}
+
 static sim_status load_network_body(sim_ctx* c, int32_t slot,
                                     const sim_params* p,
                                     const sim_network* net, void* dev_ws,
                                     uint64_t ws_bytes) {
   sim_status st = check_slot(c, slot);
   if (st != SIM_OK) return st;
+  if ((st = use_device(c)) != SIM_OK) return st;
   // from here on the slot holds no scenario, also if the call fails; as in
   // sim_unload, work already enqueued for it finishes first
   HIPCHK(c, hipStreamSynchronize(c->stream));
   Slot& S = c->slots[slot];
   S = Slot();
-  c->work_key.clear();
+  ++c->slot_gen[slot];
   if ((st = check_params(c, p)) != SIM_OK) return st;
   if ((st = check_network(c, p, net)) != SIM_OK) return st;
   if (!dev_ws) return fail(c, SIM_E_INVAL, "workspace is NULL");
@@ -464,7 +529,7 @@ static sim_status load_network_body(sim_ctx* c, int32_t slot,
   {
     int32_t min_len = INT32_MAX;
     for (int32_t i = 0; i < L; ++i) min_len = std::min(min_len, S.len[i]);
-    S.fused = !S.ring && c->cfg.step_mode == 0 &&
+    S.fused = !S.ring && c->cfg.step_mode != 1 &&
               !(p->flags & SIM_FLAG_LANE_CHANGE) && min_len >= 2 * p->vmax;
   }
   // one-kernel tiles and tiles of lane-changing links are capped in cells
@@ -602,7 +667,7 @@ static sim_status load_network_body(sim_ctx* c, int32_t slot,
   }
   HIPCHK(c, hipStreamSynchronize(s));
   S.net = true;
-  c->work_key.clear();  // slot contents changed: rebuild work lists
+  ++c->slot_gen[slot];  // slot contents changed: rebuild work lists
   return SIM_OK;
 }
 
@@ -610,13 +675,14 @@ static sim_status load_vehicles_body(sim_ctx* c, int32_t slot,
                                      const sim_vehicles* v) {
   sim_status st = check_slot(c, slot);
   if (st != SIM_OK) return st;
+  if ((st = use_device(c)) != SIM_OK) return st;
   Slot& S = c->slots[slot];
   if (!S.net) return fail(c, SIM_E_STATE, "slot %d has no network", slot);
   if (!v || v->n < 0) return fail(c, SIM_E_INVAL, "bad vehicles");
   // the per-run device state is reset below: until this load succeeds the
   // slot holds no vehicles and cannot be stepped
   S.veh = false;
-  c->work_key.clear();
+  ++c->slot_gen[slot];
   const int32_t n = v->n;
   const int vmax = S.p.vmax;
   if (n > 0 && !v->depart) return fail(c, SIM_E_INVAL, "depart is NULL");
@@ -642,6 +708,13 @@ static sim_status load_vehicles_body(sim_ctx* c, int32_t slot,
     HIPCHK(c, hipMemsetAsync(d.tile_np, 0, sizeof(int32_t) * S.n_lanes, s));
     HIPCHK(c, hipMemsetAsync(d.ring_ctr, 0, sizeof(long long) * C_N, s));
     HIPCHK(c, hipMemsetAsync(d.err, 0, sizeof(uint32_t), s));
+    // the one-kernel step starts by looking at every lane of every tile
+    std::vector<unsigned long long> live(2 * (size_t)S.n_ftiles, ~0ull);
+    HIPCHK(c, up(d.tile_live, live.data(), 2 * (int64_t)S.n_ftiles, s));
+    std::vector<int32_t> wake(2 * (size_t)S.n_ftiles, v->t0);
+    HIPCHK(c, up(d.tile_wake, wake.data(), 2 * (int64_t)S.n_ftiles, s));
+    HIPCHK(c, hipMemsetAsync(d.arr_bits, 0,
+                             sizeof(unsigned long long) * 2 * ((S.n_lanes + 63) / 64), s));
     std::vector<int32_t> none(2 * S.n_lanes, INT32_MAX);
     HIPCHK(c, up(d.claim, none.data(), 2 * S.n_lanes, s));
     HIPCHK(c, up(d.qnext, none.data(), 2 * S.n_lanes, s));
@@ -690,35 +763,71 @@ static sim_status load_vehicles_body(sim_ctx* c, int32_t slot,
     const int64_t R = n > 0 ? v->route_off[n] : 0;  // offsets checked above
     const int32_t L = S.n_links;
     const bool turn = S.p.flags & SIM_FLAG_TURN_LANES;
-    // route entries as internal link ids, then as route info words
-    std::vector<int32_t> rl(R);
-    std::vector<uint32_t> rinfo(R);
-    for (int32_t i = 0; i < n; ++i) {
-      const int64_t a = v->route_off[i], b = v->route_off[i + 1];
-      for (int64_t j = a; j < b; ++j) {
-        const int32_t e = v->route_links[j];
-        if (e < 0 || e >= L) return fail(c, SIM_E_INVAL, "vehicle %d: route link out of range", i);
-        rl[j] = S.int_of[e];
-        if (j > a && S.to[rl[j - 1]] != S.from[rl[j]])
-          return fail(c, SIM_E_INVAL, "vehicle %d: route links not connected", i);
-      }
-      for (int64_t j = a; j < b; ++j) {
-        const int32_t link = rl[j];
-        int lo = 0, hi = S.lanes[link] - 1;
-        if (turn && j + 1 < b) {
-          bool found = false;
-          for (int32_t e = S.conn_off[link]; e < S.conn_off[link + 1]; ++e)
-            if (S.conn_out[e] == rl[j + 1]) {
-              lo = S.conn_lo[e];
-              hi = S.conn_hi[e];
-              found = true;
-              break;
-            }
-          if (!found)
-            return fail(c, SIM_E_INVAL, "vehicle %d: no lane connectivity for a turn", i);
+    // route entries as internal link ids, then as route info words; the
+    // vehicles are split into contiguous ranges encoded by parallel host
+    // threads (tens of millions of entries for the largest scenarios).  The
+    // error reported is that of the lowest vehicle index, as a serial pass
+    // would report it.
+    // (rinfo is filled by the threads without being cleared first, so that
+    // its pages are first touched in parallel)
+    std::unique_ptr<uint32_t[]> rinfo(new uint32_t[std::max<int64_t>(R, 1)]);
+    auto int_link = [&](int64_t j) { return S.int_of[v->route_links[j]]; };
+    const int n_workers = host_workers(R);
+    std::vector<int32_t> bad_veh(n_workers, INT32_MAX);
+    std::vector<const char*> bad_msg(n_workers, nullptr);
+    std::vector<std::vector<int32_t>> uses(n_workers);
+    parallel_ranges(n, n_workers, [&](int32_t i0, int32_t i1, int wk) {
+      std::vector<int32_t>& use = uses[wk];
+      use.assign(L, 0);
+      for (int32_t i = i0; i < i1; ++i) {
+        const int64_t a = v->route_off[i], b = v->route_off[i + 1];
+        int32_t prev = -1;
+        for (int64_t j = a; j < b; ++j) {
+          const int32_t e = v->route_links[j];
+          if (e < 0 || e >= L) {
+            bad_veh[wk] = i;
+            bad_msg[wk] = "route link out of range";
+            return;
+          }
+          const int32_t link = S.int_of[e];
+          if (j > a && S.to[prev] != S.from[link]) {
+            bad_veh[wk] = i;
+            bad_msg[wk] = "route links not connected";
+            return;
+          }
+          ++use[link];
+          prev = link;
         }
-        rinfo[j] = rinfo_make(S.lane0[link], S.lanes[link], lo, hi, j + 1 == b);
+        for (int64_t j = a; j < b; ++j) {
+          const int32_t link = int_link(j);
+          int lo = 0, hi = S.lanes[link] - 1;
+          if (turn && j + 1 < b) {
+            const int32_t next = int_link(j + 1);
+            bool found = false;
+            for (int32_t e = S.conn_off[link]; e < S.conn_off[link + 1]; ++e)
+              if (S.conn_out[e] == next) {
+                lo = S.conn_lo[e];
+                hi = S.conn_hi[e];
+                found = true;
+                break;
+              }
+            if (!found) {
+              bad_veh[wk] = i;
+              bad_msg[wk] = "no lane connectivity for a turn";
+              return;
+            }
+          }
+          rinfo[j] = rinfo_make(S.lane0[link], S.lanes[link], lo, hi, j + 1 == b);
+        }
       }
+    });
+    {
+      int wbad = -1;
+      for (int wk = 0; wk < n_workers; ++wk)
+        if (bad_veh[wk] != INT32_MAX && (wbad < 0 || bad_veh[wk] < bad_veh[wbad]))
+          wbad = wk;
+      if (wbad >= 0)
+        return fail(c, SIM_E_INVAL, "vehicle %d: %s", bad_veh[wbad], bad_msg[wbad]);
     }
     auto ninfo_of = [&](int64_t r, int32_t i) -> int32_t {
       return r + 1 < v->route_off[i + 1] ? (int32_t)rinfo[r + 1] : 0;
@@ -727,7 +836,8 @@ static sim_status load_vehicles_body(sim_ctx* c, int32_t slot,
     // measured costs are given)
     {
       std::vector<double> use(L, 0.0);
-      for (int64_t j = 0; j < R; ++j) use[rl[j]] += 1.0;
+      for (const std::vector<int32_t>& u : uses)
+        for (int32_t l = 0; l < L; ++l) use[l] += (double)u[l];
       S.ftile_plan.assign(S.ftiles.size(), 0.0);
       int32_t l = 0;
       for (size_t t = 0; t < S.ftiles.size(); ++t)
@@ -740,12 +850,12 @@ static sim_status load_vehicles_body(sim_ctx* c, int32_t slot,
     for (int32_t i = 0; i < n; ++i) {
       const int stt = has_init ? v->init_status[i] : 0;
       if (stt == 0) {
-        wait_cnt[rl[v->route_off[i]] + 1]++;
+        wait_cnt[int_link(v->route_off[i]) + 1]++;
       } else if (stt == 1) {
         const int32_t rp = v->init_rptr[i];
         if (rp < 0 || v->route_off[i] + rp >= v->route_off[i + 1])
           return fail(c, SIM_E_INVAL, "vehicle %d: rptr out of range", i);
-        const int32_t link = rl[v->route_off[i] + rp];
+        const int32_t link = int_link(v->route_off[i] + rp);
         const int k = v->init_lane[i];
         if (k < 0 || k >= S.lanes[link] || v->init_x[i] < 0 ||
             v->init_x[i] >= S.len[link] || v->init_v[i] < 0 || v->init_v[i] > vmax)
@@ -755,7 +865,7 @@ static sim_status load_vehicles_body(sim_ctx* c, int32_t slot,
         return fail(c, SIM_E_INVAL, "vehicle %d: bad status", i);
       }
     }
-    auto link_of = [&](int32_t i) { return rl[v->route_off[i] + v->init_rptr[i]]; };
+    auto link_of = [&](int32_t i) { return int_link(v->route_off[i] + v->init_rptr[i]); };
     auto lane_of = [&](int32_t i) { return S.lane0[link_of(i)] + v->init_lane[i]; };
     std::sort(act.begin(), act.end(), [&](int32_t a, int32_t b) {
       const int32_t qa = lane_of(a), qb = lane_of(b);
@@ -796,7 +906,7 @@ static sim_status load_vehicles_body(sim_ctx* c, int32_t slot,
     {
       std::vector<int32_t> fill(wait_cnt.begin(), wait_cnt.end() - 1);
       for (int32_t i = 0; i < n; ++i)
-        if ((has_init ? v->init_status[i] : 0) == 0) wid[fill[rl[v->route_off[i]]]++] = i;
+        if ((has_init ? v->init_status[i] : 0) == 0) wid[fill[int_link(v->route_off[i])]++] = i;
       for (int32_t l = 0; l < L; ++l)
         std::sort(wid.begin() + wait_cnt[l], wid.begin() + wait_cnt[l + 1],
                   [&](int32_t a, int32_t b) {
@@ -823,8 +933,6 @@ static sim_status load_vehicles_body(sim_ctx* c, int32_t slot,
       if (wait_cnt[l] < wait_cnt[l + 1]) qrec[q0] = wrec[wait_cnt[l]];
       for (int k = 0; k < S.lanes[l]; ++k) S.lane_info[q0 + k].w = wait_cnt[l + 1];
     }
-    std::vector<int32_t> exit_t(R, -1);
-    if (v->exit_t0) std::copy(v->exit_t0, v->exit_t0 + R, exit_t.begin());
 
     Carve cv{S.ws, S.ws_net};
     carve_vehicles(cv, n, R, d, false);
@@ -844,8 +952,12 @@ static sim_status load_vehicles_body(sim_ctx* c, int32_t slot,
       HIPCHK(c, up(const_cast<int32_t*>(d.lane_qend), qend.data(), S.n_lanes, s));
     }
     HIPCHK(c, up(const_cast<int64_t*>(d.route_off), v->route_off, n + 1, s));
-    HIPCHK(c, up(const_cast<uint32_t*>(d.route_info), rinfo.data(), R, s));
-    HIPCHK(c, up(d.exit_t, exit_t.data(), R, s));
+    HIPCHK(c, up(const_cast<uint32_t*>(d.route_info), rinfo.get(), R, s));
+    if (v->exit_t0) {
+      HIPCHK(c, up(d.exit_t, v->exit_t0, R, s));
+    } else if (R > 0) {  // every entry -1: all bytes 0xFF
+      HIPCHK(c, hipMemsetAsync(d.exit_t, 0xFF, sizeof(int32_t) * (size_t)R, s));
+    }
     for (size_t r = 0; r < run_slot.size(); ++r) {
       HIPCHK(c, up(d.hot + run_slot[r], hot.data() + run_first[r], run_len[r], s));
       HIPCHK(c, up(d.cold + run_slot[r], cold.data() + run_first[r], run_len[r], s));
@@ -888,7 +1000,7 @@ static sim_status load_vehicles_body(sim_ctx* c, int32_t slot,
   HIPCHK(c, hipMemcpyAsync(c->d_descs + slot, &d, sizeof(DevScen), hipMemcpyHostToDevice, s));
   HIPCHK(c, hipStreamSynchronize(s));
   S.veh = true;
-  c->work_key.clear();
+  ++c->slot_gen[slot];
   return SIM_OK;
 }
 
@@ -965,9 +1077,10 @@ void plan_work(const sim_ctx* c, const std::vector<int32_t>& net,
 
 sim_status build_work(sim_ctx* c, const std::vector<int32_t>& net,
                       const std::vector<int32_t>& ring) {
-  std::vector<int32_t> key(net);
+  std::vector<int64_t> key;
+  for (int32_t sl : net) key.push_back((int64_t)sl << 32 | c->slot_gen[sl]);
   key.push_back(-1);
-  key.insert(key.end(), ring.begin(), ring.end());
+  for (int32_t sl : ring) key.push_back((int64_t)sl << 32 | c->slot_gen[sl]);
   if (key == c->work_key) return SIM_OK;
   WorkPlan wp;
   plan_work(c, net, ring, wp);
@@ -1076,7 +1189,7 @@ sim_status build_graph(sim_ctx* c, int K, bool profiled, hipGraphExec_t* out) {
     int step = s;
     if (n_fw > 0) {
       void* sa[] = {&descs, &fslot, &fwork, &step};
-      add(step_kernel(fbatched), n_fw, kWave, 0, sa);
+      add(step_kernel(fbatched, skip_lanes(c, n_fw)), n_fw, kWave, 0, sa);
       mark(3);
     }
     if (n_tw > 0) {
@@ -1269,7 +1382,8 @@ static sim_status step_body(sim_ctx* c, const int32_t* slots, int32_t n_slots,
     for (int32_t s = 0; s < rest; ++s) {
       if (n_fw > 0) {
         st = timed(c, 3, [&] {
-          return launch_step(c->d_descs, c->fused_slot, c->d_work, n_fw, s, c->stream);
+          return launch_step(c->d_descs, c->fused_slot, c->d_work, n_fw, s,
+                             skip_lanes(c, n_fw), c->stream);
         });
         if (st != SIM_OK) return st;
       }
@@ -1331,7 +1445,8 @@ static sim_status step_noalloc_body(sim_ctx* c, const int32_t* slots,
   if (wp.n_net > 0) {
     for (int32_t s = 0; s < n_steps; ++s) {
       if (n_fw > 0)
-        HIPCHK(c, launch_step(c->d_descs, wp.fused_slot, d_work, n_fw, s, c->stream));
+        HIPCHK(c, launch_step(c->d_descs, wp.fused_slot, d_work, n_fw, s,
+                              skip_lanes(c, n_fw), c->stream));
       if (n_tw > 0) {
         HIPCHK(c, launch_front(c->d_descs, wp.single_slot, d_work + n_fw, n_tw,
                                c->cfg.back_pieces, s, wp.lc_words, c->stream));
@@ -1487,7 +1602,7 @@ extern "C" sim_status sim_unload(sim_ctx* c, int32_t slot) {
   if (st != SIM_OK) return st;
   HIPCHK(c, hipStreamSynchronize(c->stream));
   c->slots[slot] = Slot();
-  c->work_key.clear();
+  ++c->slot_gen[slot];
   return SIM_OK;
 }
 

@@ -22,6 +22,10 @@ hipError_t hipGetDevice(int* deviceId) {
   return hipSuccess;
 }
 
+hipError_t hipSetDevice(int deviceId) {
+  return deviceId == 0 ? hipSuccess : hipErrorInvalidDevice;
+}
+
 hipError_t hipMalloc(void** ptr, size_t size) {
   *ptr = std::aligned_alloc(256, (size + 255) / 256 * 256);
   return *ptr ? hipSuccess : hipErrorOutOfMemory;
@@ -110,10 +114,11 @@ hipError_t launch_back(const DevScen*, int, const int4*, int, int, int,
                        hipStream_t) {
   return hipSuccess;
 }
-hipError_t launch_step(const DevScen*, int, const int4*, int, int, hipStream_t) {
+hipError_t launch_step(const DevScen*, int, const int4*, int, int, bool,
+                       hipStream_t) {
   return hipSuccess;
 }
-void* step_kernel(bool) { return &kernel_token; }
+void* step_kernel(bool, bool) { return &kernel_token; }
 void* front_kernel(bool) { return &kernel_token; }
 void* back_kernel(bool) { return &kernel_token; }
 void* advance_kernel() { return &kernel_token; }

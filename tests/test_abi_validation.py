@@ -127,7 +127,7 @@ def test_context_configuration_checks(lib):
     assert create(abi_version=sim.ABI_VERSION + 1) == sim.E_ABI
     for kw in ({"max_slots": 0}, {"max_slots": 65537}, {"tile_lanes": -1},
                {"tile_lanes": 65}, {"back_pieces": 9}, {"back_pieces": -1},
-               {"step_mode": 2}, {"tile_cells": 63}, {"tile_cells": 65537},
+               {"step_mode": 3}, {"step_mode": -1}, {"tile_cells": 63}, {"tile_cells": 65537},
                {"graph_steps": 4097}, {"reserved": 1}):
         assert create(**kw) == sim.E_INVAL, kw
     assert lib.sim_create(None, None) == sim.E_INVAL

@@ -18,7 +18,7 @@ def _ctx(mode, **kw):
     return Context(max_slots=1, step_mode=mode, **kw)
 
 
-@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("mode", [0, 1, 2])
 @pytest.mark.parametrize("vmax,p", [(1, "0"), (1, "1"), (3, "0.5"),
                                     (7, "0"), (7, "0.2"), (5, "1")])
 def test_speed_and_slowdown_extremes(mode, vmax, p):
@@ -31,7 +31,7 @@ def test_speed_and_slowdown_extremes(mode, vmax, p):
     ctx.close()
 
 
-@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("mode", [0, 1, 2])
 def test_everyone_departs_at_once(mode):
     # long parking queues on every origin link, all released at t = 0
     scen = S.grid_scenario(5, 5, 64, 3000, T=300, depart_max=0, seed=12)

@@ -37,7 +37,8 @@ def test_portland_full_run_matches_oracle(portland):
 # another tile's data must see the previous step's values regardless.
 @pytest.mark.parametrize("mode,lanes,cells,pieces,graph", [
     (1, 16, 0, 1, -1), (1, 16, 0, 8, 200), (1, 1, 0, 1, 64),
-    (0, 1, 0, 1, 64), (0, 4, 256, 1, 32), (0, 64, 65536, 1, 64)])
+    (0, 1, 0, 1, 64), (0, 4, 256, 1, 32), (0, 64, 65536, 1, 64),
+    (2, 16, 0, 1, 64), (2, 1, 0, 1, 64)])
 def test_portland_configs_agree(portland, mode, lanes, cells, pieces, graph):
     from paper_cs_0105004_amd.sim import Context
     ref = Context(max_slots=1)

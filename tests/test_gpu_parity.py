@@ -65,14 +65,24 @@ def sim_two_kernel():
     ctx.close()
 
 
+@pytest.fixture(scope="module")
+def sim_skip():
+    # one kernel per step, skipping lanes that are empty and stay empty
+    from paper_cs_0105004_amd.sim import Context
+    ctx = Context(max_slots=2, step_mode=2)
+    yield ctx
+    ctx.close()
+
+
 # the worked cases and the cases on either side of each comparison of the
 # lane-change and node rules, in both step forms; each is checked against
 # its hand-worked outcome and against the oracle's complete state
-@pytest.mark.parametrize("mode", [0, 1], ids=["one_kernel", "two_kernel"])
+@pytest.mark.parametrize("mode", [0, 1, 2],
+                         ids=["one_kernel", "two_kernel", "skip_idle"])
 @pytest.mark.parametrize("case", load_cases() + load_cases(BOUNDARIES),
                          ids=lambda c: c["name"])
-def test_hand_worked_cases(sim, sim_two_kernel, case, mode):
-    ctx = sim if mode == 0 else sim_two_kernel
+def test_hand_worked_cases(sim, sim_two_kernel, sim_skip, case, mode):
+    ctx = (sim, sim_two_kernel, sim_skip)[mode]
     scen = build(case)
     print("case", case["name"], "mode", mode, flush=True)
     ctx.load(0, scen)
@@ -140,6 +150,38 @@ def test_medium_grid_ragged_tiles(sim):
     run_side_by_side(sim, 0, scen, 500, every=100, full_at=(250,))
 
 
+def test_skip_idle_batched_slots_come_and_go():
+    """Idle-lane skipping with slots loaded and unloaded between calls and
+    uneven progress: every slot equals the oracle (a restart from a saved
+    state begins with a step that looks at every lane)."""
+    from paper_cs_0105004_amd.sim import Context
+    ctx = Context(max_slots=3, step_mode=2, tile_lanes=1)
+    a = S.portland_like(scale=0.05, T=900, depart_max=600, seed=21)
+    b = S.portland_like(scale=0.2, T=900, depart_max=600, seed=22)
+    oa, ob = oracle.OracleSim(a), oracle.OracleSim(b)
+    ctx.load(0, a)
+    ctx.step(0, 101)
+    oa.step(101)
+    ctx.load(1, b)
+    ctx.step([0, 1], 250)
+    oa.step(250)
+    ob.step(250)
+    assert_same_stats(ctx.stats(1), ob.stats(), "b at 250")
+    mid = ctx.state(0)
+    ctx.unload(0)
+    ctx.load(2, a.with_state(mid, 351))
+    ctx.step(2, 77)
+    oa.step(77)
+    ctx.step([1, 2], 300)
+    oa.step(300)
+    ob.step(300)
+    # (the restarted slot's counters start again at its restart)
+    assert ctx.stats(2)["hash"] == oa.stats()["hash"]
+    assert_same_state(ctx.state(2), oa.state(), "a")
+    assert_same_state(ctx.state(1), ob.state(), "b")
+    ctx.close()
+
+
 def test_batched_slots_equal_solo(sim):
     scens = [small_grid(seed=31), small_grid(S.FLAG_LANE_CHANGE, seed=32),
              S.loop_of_links([12, 30, 9], 20, p="0.3", seed=3, T=300),
@@ -187,10 +229,11 @@ def test_dense_lanes_many_vehicle_groups(tile_lanes, pieces, flags):
         ctx.close()
 
 
-@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("mode", [0, 1, 2])
 def test_step_modes_agree_with_oracle(mode):
     # mode 0 runs this scenario (no lane changes, links >= 2 vmax cells) with
-    # one kernel per step, mode 1 with the lane-change and move kernels
+    # one kernel per step, mode 1 with the lane-change and move kernels,
+    # mode 2 with one kernel that skips idle lanes
     from paper_cs_0105004_amd.sim import Context
     scen = S.portland_like(scale=0.02, T=400)
     assert scen.link_len.min() >= 2 * scen.vmax
@@ -198,17 +241,18 @@ def test_step_modes_agree_with_oracle(mode):
     ctx.profile(True)
     run_side_by_side(ctx, 0, scen, 400, every=40, full_at=(200,))
     kt = ctx.kernel_times()
-    if mode == 0:
+    if mode != 1:
         assert kt["step"][0] == 400 and kt["front"][0] == 0
     else:
         assert kt["step"][0] == 0 and kt["front"][0] == 400
     ctx.close()
 
 
-def test_one_kernel_step_with_graphs_and_restart():
+@pytest.mark.parametrize("mode", [0, 2])
+def test_one_kernel_step_with_graphs_and_restart(mode):
     from paper_cs_0105004_amd.sim import Context
     scen = S.portland_like(scale=0.05, T=600)
-    a = Context(max_slots=2, graph_steps=32)
+    a = Context(max_slots=2, graph_steps=32, step_mode=mode)
     a.load(0, scen)
     a.step(0, 333)
     mid = a.state(0)

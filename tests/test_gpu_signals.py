@@ -11,7 +11,7 @@ from parity import assert_same_state, assert_same_stats, run_side_by_side
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("mode", [0, 1, 2])
 @pytest.mark.parametrize("cycle,red", [(40, 20), (60, 30), (7, 3)])
 def test_signalised_grid(mode, cycle, red):
     from paper_cs_0105004_amd.sim import Context
@@ -99,7 +99,7 @@ def _red_lead_beats_green(scen, st, t):
     return any(red < green for red, green in best.values())
 
 
-@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("mode", [0, 1, 2])
 def test_restart_at_a_red_phase(mode):
     """A restart from a saved state while lights are red: a lead vehicle at
     a red light claims nothing in the restart step, so a green candidate of
