@@ -55,12 +55,15 @@ class FakeEvent:
         pass
 
 
-def server(max_slots, budget, sizes, chunk):
+def server(max_slots, budget, sizes, chunk, background=False):
     srv = object.__new__(serve.Server)  # no GPU: the constructor is bypassed
-    srv.torch = types.SimpleNamespace(cuda=types.SimpleNamespace(Event=FakeEvent))
+    srv.torch = types.SimpleNamespace(cuda=types.SimpleNamespace(
+        Event=FakeEvent, set_device=lambda d: None))
+    srv.device = 0
     srv.ctx = FakeContext(max_slots, sizes)
     srv.budget, srv.max_slots, srv.chunk = budget, max_slots, chunk
     srv.read_exit_times, srv.log = True, []
+    srv.background = background
     return srv
 
 
@@ -124,3 +127,47 @@ def test_summary_percentiles():
     assert out["p50_latency_s"] in (50.0, 51.0)
     assert out["p99_latency_s"] == 99.0 and out["max_latency_s"] == 100.0
     assert serve.percentile([], 0.5) != serve.percentile([], 0.5)  # nan
+
+
+class SlowLoadContext(FakeContext):
+    """Loads block until the driving thread has stepped the runs already
+    loaded a given number of times (or nothing else runs)."""
+
+    def __init__(self, max_slots, sizes, steps_before_load):
+        super().__init__(max_slots, sizes)
+        import threading
+        self.cv = threading.Condition()
+        self.n_steps = 0
+        self.wait_for = steps_before_load
+
+    def load(self, slot, scen):
+        with self.cv:
+            self.cv.wait_for(lambda: self.n_steps >= self.wait_for
+                             or not self.loaded, timeout=5.0)
+            super().load(slot, scen)
+
+    def step(self, slots, n):
+        with self.cv:
+            super().step(slots, n)
+            self.n_steps += 1
+            self.cv.notify_all()
+
+
+def test_background_loads_keep_the_running_slots_stepping():
+    sizes = {0: 10, 1: 10, 2: 10}
+    reqs = [serve.Request(0, 0.0, scen(0, 640)),
+            serve.Request(1, 0.0, scen(1, 100)),
+            serve.Request(2, 0.0, scen(2, 50))]
+    srv = server(max_slots=3, budget=100, sizes=sizes, chunk=64,
+                 background=True)
+    srv.ctx = SlowLoadContext(3, sizes, steps_before_load=3)
+    res = srv.run(reqs, realtime=False)
+    assert sorted(r.rid for r in res) == [0, 1, 2]
+    for r in res:
+        assert r.stats["t"] == reqs[r.rid].scen.T
+    log = srv.ctx.log
+    # the first run was stepped while the others were still loading
+    first_other = min(i for i, ev in enumerate(log)
+                      if ev[0] == "load" and ev[2] != 0)
+    assert sum(1 for ev in log[:first_other] if ev[0] == "step") >= 3
+    assert [ev for ev in log if ev[0] == "unload"] and not srv.ctx.loaded
