@@ -137,7 +137,19 @@ def family_of(kinds) -> str:
 # of known size (x 2.0 and x 1.0).  Valid only for the kernel sources with
 # this digest (of the kernel's family) and for exactly that window and tile
 # shape; any other run reports null.
-MEASURED_TRAFFIC = {}
+MEASURED_TRAFFIC = {
+    "e0657611fe69b54c": {  # step.hip family
+        "portland": [
+            # k_step<false, false>, default tiles, window [1800, 1820):
+            # FETCH 3013.6 KiB x 2.0 + WRITE 1940.9 KiB x 1.0
+            {"window": (1800, 20), "tiles": (0, 0),
+             "bytes_per_launch": 7968.1 * 1024},
+            # window [1800, 1900): FETCH 2860.0 x 2.0 + WRITE 1844.4
+            {"window": (1800, 100), "tiles": (0, 0),
+             "bytes_per_launch": 7564.4 * 1024},
+        ],
+    },
+}
 
 
 def measured_traffic(family: str, workload: str, window, tiles=(0, 0)):
@@ -435,7 +447,7 @@ def bench_batched(args):
     ctx = Context(max_slots=n, tile_lanes=tune["tile_lanes"],
                   back_pieces=tune["back_pieces"],
                   graph_steps=tune["graph_steps"],
-                  tile_cells=tune["tile_cells"])
+                  tile_cells=tune["tile_cells"], step_mode=args.step_mode)
 
     def load_all(cs):
         for k, sc in enumerate(scens):
@@ -731,6 +743,9 @@ def main():
                     metavar="BYTES", help="only run plain copies of BYTES")
     ap.add_argument("--window", type=float, default=60.0,
                     help="serving: seconds of Poisson arrivals")
+    ap.add_argument("--step-mode", type=int, default=0,
+                    help="the library's step_mode (2: the one-kernel step "
+                         "skips idle lanes); single and batched workloads")
     ap.add_argument("--counter-pass", action="store_true",
                     help="only the timed window once (fresh load, untimed "
                          "advance to the demand peak, K steps), for a "
@@ -774,7 +789,7 @@ def counter_pass(args):
         tiles = dict(tile_lanes=args.tile_lanes, tile_cells=args.tile_cells)
     n = len(scens)
     slots = list(range(n))
-    ctx = Context(max_slots=n, **tiles)
+    ctx = Context(max_slots=n, step_mode=args.step_mode, **tiles)
     for k, sc in enumerate(scens):
         ctx.load(k, sc)
     T = scens[0].T
@@ -832,7 +847,7 @@ def bench_single(args):
         raise SystemExit(f"--steps must be 1..{T} (the window inside the "
                          f"horizon)")
     ctx = Context(max_slots=2, tile_lanes=args.tile_lanes,
-                  tile_cells=args.tile_cells)
+                  tile_cells=args.tile_cells, step_mode=args.step_mode)
 
     # warm-up on a throw-away copy
     log(f"bench: warmup {args.warmup} steps")

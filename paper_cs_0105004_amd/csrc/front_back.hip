@@ -250,11 +250,6 @@ __device__ int lane_change_tile(const DevScen& S, int t, int nl,
     T.vp[i] = vi - nv;
     T.mv[i] = 0;
   }
-  for (int q = i; q < Wt; q += kWave) {
-    Z.occ[q] = 0u;
-    Z.rgt[q] = 0u;
-    Z.lft[q] = 0u;
-  }
   __syncthreads();
 
   // the first kLcRes * kWave vehicles, loaded once (threads past V load the
@@ -274,6 +269,47 @@ __device__ int lane_change_tile(const DevScen& S, int t, int nl,
     }
   }
   const int f_rest = kLcRes * kWave;  // first vehicle of the loops below
+
+  // A vehicle can only change lanes if it must (it is outside the lanes of
+  // its next turn) or if its own lane holds it back: fewer than
+  // min(v+1, vmax) empty cells ahead.  Both follow from its record and the
+  // record ahead of it in its lane (the tile's vehicles are numbered lane by
+  // lane, lead first), so when no vehicle of the tile qualifies the sub-step
+  // changes nothing and the lattice is never built.  Vehicles past the
+  // first kLcRes * kWave count as qualifying.
+  {
+    const int vmax = S.vmax;
+    bool want = V > f_rest;
+    int prev_x = 0;
+#pragma unroll
+    for (int u = 0; u < kLcRes; ++u) {
+      const int f = u * kWave + i;
+      const int x = xvf_x(rhw[u].x);
+      int px = __shfl_up(x, 1);
+      if (u > 0) {
+        const int wrap = __shfl(prev_x, kWave - 1);
+        if (i == 0) px = wrap;
+      }
+      prev_x = x;
+      if (f < V) {
+        const uint32_t meta = (uint32_t)T.info[rln[u]].y;
+        const uint32_t fl = xvf_fl(rhw[u].x);
+        const int k = lmeta_k(meta), len = lmeta_len(meta);
+        const bool lead = f == T.vp[rln[u]];
+        const int own = min(vmax, lead ? len - 1 - x : px - x - 1);
+        if (k < fl_lo(fl) || k > fl_hi(fl) ||
+            own < min(xvf_v(rhw[u].x) + 1, vmax))
+          want = true;
+      }
+    }
+    if (__ballot(want) == 0ull) return 0;
+  }
+  for (int q = i; q < Wt; q += kWave) {
+    Z.occ[q] = 0u;
+    Z.rgt[q] = 0u;
+    Z.lft[q] = 0u;
+  }
+  __syncthreads();
 
   // occupancy
 #pragma unroll
