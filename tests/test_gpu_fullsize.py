@@ -54,30 +54,51 @@ def test_portland_configs_agree(portland, mode, lanes, cells, pieces, graph):
     alt.close()
 
 
-def test_batched_replications_full_size_sampled():
-    # all 64 replications (417k links, 4.1M vehicles) in the launch
-    # configuration the batched benchmark picks, full 3,600 steps; the three
-    # smallest are compared with the oracle vehicle by vehicle, every one
-    # against counters that hold at any size
+def _digests(state):
+    import hashlib
     import numpy as np
+    out = {}
+    for key, dt in (("status", np.int8), ("link", np.int32),
+                    ("lane", np.int8), ("x", np.int32), ("v", np.int8),
+                    ("rptr", np.int32), ("exit_t", np.int32)):
+        a = np.ascontiguousarray(state[key],
+                                 dtype=np.dtype(dt).newbyteorder("<"))
+        out[key] = hashlib.sha256(a.tobytes()).hexdigest()
+    return out
+
+
+@pytest.mark.parametrize("tiles", [(64, 16384), (64, 12288)])
+def test_batched_replications_full_size_match_oracle_checkpoints(tiles):
+    """All 64 replications (417k links, 4.1M vehicles) stepped together in a
+    launch configuration the batched benchmark uses, over the full 3,600
+    steps, against the oracle's checkpoints of every replication at
+    t = 1,800 and 3,600 (golden/make_batched_checkpoints.py): every counter,
+    the state hash and SHA-256 digests of every per-vehicle array and of the
+    exit times."""
+    import json
+    import os
     from paper_cs_0105004_amd.sim import Context
+    with open(os.path.join(os.path.dirname(os.path.abspath(__file__)),
+                           "golden", "batched_checkpoints.json")) as f:
+        golden = json.load(f)["replications"]
     scens = S.batched_scenarios()
-    ctx = Context(max_slots=len(scens), tile_lanes=64, tile_cells=16384,
-                  graph_steps=64)
+    assert len(golden) == len(scens) == 64
+    ctx = Context(max_slots=len(scens), tile_lanes=tiles[0],
+                  tile_cells=tiles[1], graph_steps=64)
     for k, sc in enumerate(scens):
         ctx.load(k, sc)
-    ctx.step(list(range(len(scens))), 3600)
-    for k, sc in enumerate(scens):
-        st = ctx.stats(k)
-        assert st["dev_err"] == 0
-        assert st["n_waiting"] + st["n_active"] + st["n_arrived"] == sc.n_veh
-        assert st["insertions"] == sc.n_veh - st["n_waiting"]
-        assert st["exits"] == st["n_arrived"]
-    order = np.argsort([sc.n_veh for sc in scens])[:3]
-    for k in order:
-        o = oracle.OracleSim(scens[k])
-        o.step(3600)
-        print("replication", k, scens[k].n_links, "links", flush=True)
-        assert_same_stats(ctx.stats(k), o.stats(), f"replication {k}")
-        assert_same_state(ctx.state(k), o.state(), f"replication {k}")
+    t = 0
+    for c in (0, 1):
+        cp = golden[0]["checkpoints"][c]["stats"]["t"]
+        ctx.step(list(range(len(scens))), cp - t)
+        t = cp
+        print("batched checkpoint", cp, flush=True)
+        for k, sc in enumerate(scens):
+            want = golden[k]["checkpoints"][c]
+            st = ctx.stats(k)
+            assert st["dev_err"] == 0
+            for key, v in want["stats"].items():
+                assert st[key] == v, f"replication {k} t={cp} {key}"
+            assert _digests(ctx.state(k)) == want["sha256"], \
+                f"replication {k} t={cp}"
     ctx.close()
