@@ -140,13 +140,27 @@ def family_of(kinds) -> str:
 MEASURED_TRAFFIC = {
     "e0657611fe69b54c": {  # step.hip family
         "portland": [
-            # k_step<false, false>, default tiles, window [1800, 1820):
-            # FETCH 3013.6 KiB x 2.0 + WRITE 1940.9 KiB x 1.0
-            {"window": (1800, 20), "tiles": (0, 0),
+            # k_step<false, false>, the default 16-lane / 1,024-cell tiles,
+            # window [1800, 1820): FETCH 3284.4 KiB x 2.0 + WRITE 2272.0 KiB
+            {"window": (1800, 20), "tiles": (16, 1024),
+             "bytes_per_launch": 8840.8 * 1024},
+            # window [1800, 1900): FETCH 3161.5 x 2.0 + WRITE 2175.0
+            {"window": (1800, 100), "tiles": (16, 1024),
+             "bytes_per_launch": 8498.0 * 1024},
+            # k_step<false, false>, 16-lane / 2,048-cell tiles, window
+            # [1800, 1820): FETCH 3013.6 KiB x 2.0 + WRITE 1940.9 KiB x 1.0
+            {"window": (1800, 20), "tiles": (16, 2048),
              "bytes_per_launch": 7968.1 * 1024},
             # window [1800, 1900): FETCH 2860.0 x 2.0 + WRITE 1844.4
-            {"window": (1800, 100), "tiles": (0, 0),
+            {"window": (1800, 100), "tiles": (16, 2048),
              "bytes_per_launch": 7564.4 * 1024},
+        ],
+        "batched": [
+            # k_step<true, false>, 64 replications, 64-lane / 12,288-cell
+            # tiles, window [1800, 1900): FETCH 52438.9 KiB x 2.0 + WRITE
+            # 34041.3 KiB x 1.0
+            {"window": (1800, 100), "tiles": (64, 12288),
+             "bytes_per_launch": 138919.1 * 1024},
         ],
     },
 }
@@ -959,9 +973,14 @@ def bench_single(args):
     ctx.profile(False)
     assert ctx.stats(0)["hash"] == st_b["hash"], "timing pass diverged"
     tiling = ctx.tiling(0)
+    # the tile shape the traffic was measured with: the library's defaults
+    # (16 lanes / 1,024 cells for one-kernel scenarios, 32 / 4,096 with lane
+    # changes) unless given
+    lc = args.workload == "large"
+    tiles = (args.tile_lanes or (32 if lc else 16),
+             args.tile_cells or (4096 if lc else 1024))
     roof = roofline_from(kt, [win], region_ms, workload=args.workload,
-                         window=(t0, K),
-                         tiles=(args.tile_lanes, args.tile_cells))
+                         window=(t0, K), tiles=tiles)
     with_copy_reference(roof)
     walls = sorted(r[0] for r in runs)
     cfg = dict(cfg, timed_window=[t0, t0 + K], peak_active=n_peak,

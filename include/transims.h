@@ -101,7 +101,7 @@ typedef struct {
   int32_t tile_cells;   /* one-kernel step, and scenarios with lane
                            changes: a tile also stops at this many cells
                            (len x lanes; a longer link is a tile of its
-                           own), 64..65536; 0 = default (2048; 4096 for
+                           own), 64..65536; 0 = default (1024; 4096 for
                            scenarios with lane changes)                     */
   int32_t reserved;     /* must be 0                                        */
 } sim_config;
