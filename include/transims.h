@@ -292,9 +292,9 @@ sim_status sim_stats(sim_ctx* ctx, int32_t slot, sim_stats_t* out);
    left each link of its plan, the link travel times the iteration between
    runs feeds back (Section "Introduction").  Host arrays are owned by the
    caller.  Errors: SIM_E_STATE for an unloaded slot, SIM_E_DEVICE if a
-   copy fails.  The export goes through a
-   temporary device buffer of 15 bytes per vehicle, allocated and freed
-   inside the call. */
+   copy fails.  The export goes through a staging area of 15 bytes per
+   vehicle in the slot's workspace (sim_footprint counts it), so the call
+   allocates nothing. */
 sim_status sim_read_state(sim_ctx* ctx, int32_t slot, int8_t* status,
                           int32_t* link, int8_t* lane, int32_t* x, int8_t* v,
                           int32_t* rptr, int32_t* exit_t);

@@ -54,6 +54,7 @@ struct Slot {
   std::vector<int8_t> conn_lo, conn_hi;
   std::vector<int2> tiles, ftiles;  // move sub-step / lane-change sub-step
   std::vector<int4> plans;  // signal plans {cycle, red, offset mod cycle, 0}
+  ExportBufs exp{};         // state export staging in the workspace
   std::vector<double> weight;  // internal order
   std::vector<double> ftile_w;  // summed link weight of each tile
   bool measured = false;        // weights are measured costs (link_cost)
@@ -209,7 +210,11 @@ void carve_network(Carve& cv, const NetDims& nd, DevScen& d, bool ring) {
   d.err = cv.take<uint32_t>(1);
 }
 
-void carve_vehicles(Carve& cv, int64_t n, int64_t R, DevScen& d, bool ring) {
+// vehicle arrays, then the staging area sim_read_state exports the
+// per-vehicle state through (15 bytes per vehicle), so that reading a
+// state back allocates nothing
+void carve_vehicles(Carve& cv, int64_t n, int64_t R, DevScen& d, bool ring,
+                    ExportBufs& o) {
   d.wait_rec = cv.take<int4>(ring ? 0 : n);
   d.route_off = cv.take<int64_t>(ring ? 0 : n + 1);
   d.route_info = cv.take<uint32_t>(R);
@@ -217,6 +222,12 @@ void carve_vehicles(Carve& cv, int64_t n, int64_t R, DevScen& d, bool ring) {
   d.ring_x = cv.take<int32_t>(ring ? n : 0);
   d.ring_v = cv.take<int32_t>(ring ? n : 0);
   d.ring_id = cv.take<int32_t>(ring ? n : 0);
+  o.status = cv.take<int8_t>(n);
+  o.link = cv.take<int32_t>(n);
+  o.lane = cv.take<int8_t>(n);
+  o.x = cv.take<int32_t>(n);
+  o.v = cv.take<int8_t>(n);
+  o.rptr = cv.take<int32_t>(n);
 }
 
 sim_status check_params(sim_ctx* c, const sim_params* p) {
@@ -453,7 +464,8 @@ static sim_status footprint_body(const sim_ctx* cc, const sim_params* p,
     if (veh->n < 0) return fail(c, SIM_E_INVAL, "negative vehicle count");
     if (!ring && (st = check_route_off(c, veh->n, veh->route_off)) != SIM_OK) return st;
     const int64_t R = (!ring && veh->n > 0) ? veh->route_off[veh->n] : 0;
-    carve_vehicles(cv, veh->n, R, d, ring);
+    ExportBufs o{};
+    carve_vehicles(cv, veh->n, R, d, ring, o);
   }
   *bytes = cv.off + 256;
   return SIM_OK;
@@ -755,7 +767,7 @@ static sim_status load_vehicles_body(sim_ctx* c, int32_t slot,
       rid[j] = idx[j];
     }
     Carve cv{S.ws, S.ws_net};
-    carve_vehicles(cv, n, 0, d, true);
+    carve_vehicles(cv, n, 0, d, true, S.exp);
     if (cv.off > S.ws_bytes)
       return fail(c, SIM_E_NOMEM, "workspace of %llu bytes, scenario needs %llu",
                   (unsigned long long)S.ws_bytes, (unsigned long long)cv.off);
@@ -943,7 +955,7 @@ static sim_status load_vehicles_body(sim_ctx* c, int32_t slot,
     }
 
     Carve cv{S.ws, S.ws_net};
-    carve_vehicles(cv, n, R, d, false);
+    carve_vehicles(cv, n, R, d, false, S.exp);
     if (cv.off > S.ws_bytes)
       return fail(c, SIM_E_NOMEM, "workspace of %llu bytes, scenario needs %llu",
                   (unsigned long long)S.ws_bytes, (unsigned long long)cv.off);
@@ -1113,17 +1125,21 @@ sim_status build_work(sim_ctx* c, const std::vector<int32_t>& net,
   }
   const std::vector<int4>& work = wp.work;
   const std::vector<int32_t>& list = wp.list;
+  // (the lists grow by half again when they must, so that slots coming
+  // and going seldom reallocate them)
   if (work.size() > c->work_cap) {
     if (c->d_work) HIPCHK(c, hipFree(c->d_work));
     c->d_work = nullptr;
-    HIPCHK(c, hipMalloc(&c->d_work, sizeof(int4) * std::max<size_t>(work.size(), 1)));
-    c->work_cap = work.size();
+    const size_t cap = std::max(work.size(), c->work_cap + c->work_cap / 2);
+    HIPCHK(c, hipMalloc(&c->d_work, sizeof(int4) * std::max<size_t>(cap, 1)));
+    c->work_cap = cap;
   }
   if (list.size() > c->list_cap) {
     if (c->d_list) HIPCHK(c, hipFree(c->d_list));
     c->d_list = nullptr;
-    HIPCHK(c, hipMalloc(&c->d_list, sizeof(int) * std::max<size_t>(list.size(), 1)));
-    c->list_cap = list.size();
+    const size_t cap = std::max(list.size(), c->list_cap + c->list_cap / 2);
+    HIPCHK(c, hipMalloc(&c->d_list, sizeof(int) * std::max<size_t>(cap, 1)));
+    c->list_cap = cap;
   }
   HIPCHK(c, up(c->d_work, work.data(), (int64_t)work.size(), c->stream));
   HIPCHK(c, up(c->d_list, list.data(), (int64_t)list.size(), c->stream));
@@ -1511,21 +1527,7 @@ static sim_status read_state_body(sim_ctx* c, int32_t slot, int8_t* status,
   const Slot& S = c->slots[slot];
   if (!S.net || !S.veh) return fail(c, SIM_E_STATE, "slot %d is not loaded", slot);
   const int64_t n = S.n_veh;
-  auto carve_out = [n](Carve& cv, ExportBufs& o) {
-    o.status = cv.take<int8_t>(n);
-    o.link = cv.take<int32_t>(n);
-    o.lane = cv.take<int8_t>(n);
-    o.x = cv.take<int32_t>(n);
-    o.v = cv.take<int8_t>(n);
-    o.rptr = cv.take<int32_t>(n);
-  };
-  ExportBufs o;
-  Carve measure{nullptr, 0};
-  carve_out(measure, o);
-  uint8_t* buf = nullptr;
-  HIPCHK(c, hipMalloc(&buf, measure.off));
-  Carve cv{buf, 0};
-  carve_out(cv, o);
+  const ExportBufs& o = S.exp;  // staging in the slot's workspace
   hipError_t e = launch_export(c->d_descs + slot, o, (int)n, S.n_links, S.n_lanes,
                                S.ring ? 1 : 0, c->stream);
   const char* what = "export kernels";
@@ -1546,7 +1548,6 @@ static sim_status read_state_body(sim_ctx* c, int32_t slot, int8_t* status,
     e = hipStreamSynchronize(c->stream);
     what = "synchronize";
   }
-  (void)hipFree(buf);
   if (e != hipSuccess)
     return fail(c, SIM_E_DEVICE, "read_state: %s: %s", what, hipGetErrorString(e));
   return SIM_OK;
