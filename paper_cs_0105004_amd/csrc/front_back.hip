@@ -111,8 +111,10 @@ __device__ int lc_decide(const DevScen& S, const uint32_t* wk, int wpl,
     }
   }
   if (best < 0) return -1;
-  if ((uint64_t)veh_draw((uint32_t)id, (uint32_t)t, 0u, S.key0, S.key1) >=
-      S.lc_thr)
+  // a threshold of 2^32 takes every draw, which is then not made
+  if (S.lc_thr < (1ull << 32) &&
+      (uint64_t)veh_draw((uint32_t)id, (uint32_t)t, 0u, S.key0, S.key1) >=
+          S.lc_thr)
     return -1;
   return best;
 }
@@ -127,14 +129,23 @@ __device__ __forceinline__ int wave_incl_scan(int v) {
   return v;
 }
 
-// Largest j < n with pre[j] <= f (pre ascending, pre[0] = 0 <= f)
-__device__ __forceinline__ int lc_find(const int* pre, int n, int f) {
-  int lo = 0, hi = n;
-  while (hi - lo > 1) {
-    const int mid = (lo + hi) >> 1;
-    if (pre[mid] <= f) lo = mid;
-    else hi = mid;
+// Largest j < n with pre[j] <= f (pre ascending, pre[0] = 0 <= f, n at
+// most kMaxTileLanes), with pre[j] in *pj.  The steps are the fixed powers
+// of two below kMaxTileLanes, taken with no branch at all, so the compiler
+// overlaps the searches of a thread's several vehicles instead of running
+// one search after another.
+__device__ __forceinline__ int lc_find(const int* pre, int n, int f,
+                                       int* pj = nullptr) {
+  int lo = 0, plo = 0;
+#pragma unroll
+  for (int s = kMaxTileLanes / 2; s >= 1; s >>= 1) {
+    const int j = min(lo + s, n - 1);
+    const int pv = pre[j];
+    const bool up = pv <= f;
+    lo = up ? j : lo;
+    plo = up ? pv : plo;
   }
+  if (pj) *pj = plo;
   return lo;
 }
 
@@ -151,20 +162,53 @@ struct LcTile {
   uint32_t* rw;      // rear record's xvf word after the sub-step
 };
 
-// Lane and record slot of vehicle f of the tile's lattice
-// (f < V; lanes in order, each lane lead first)
-__device__ __forceinline__ void lc_locate(const LcTile& T, int nl, int f,
-                                          int& ln, int& slot) {
-  ln = lc_find(T.vp, nl, f);
-  slot = rec_slot(T.info[ln].x, T.hp[ln], lmeta_len((uint32_t)T.info[ln].y),
-                  f - T.vp[ln]);
+// What a lane thread (thread j < nl) holds of lane j for finding records:
+// the lane's first vehicle in the tile's numbering, the start of its
+// current ring half, and its ring head | length << 16.
+struct LcLane {
+  int vp, org, hl;
+};
+
+// Lane and record slot of vehicle f of the tile's numbering (lanes in
+// order, each lane lead first), for F <= f <= Fl < F + kWave with F and Fl
+// the same in every thread; called by the whole wave.  The lanes that hold
+// vehicles F to Fl follow from two ballots over the lane threads' first
+// vehicles; each thread then counts the lanes of that range that start at
+// or before its vehicle, and takes the ring position from the lane
+// thread's registers.
+__device__ __forceinline__ void lc_locate(const LcLane& R, int nl, int F,
+                                          int Fl, int f, int& ln, int& slot) {
+  const bool lt = (int)threadIdx.x < nl;
+  const int l0 = __popcll(__ballot(lt && R.vp <= F)) - 1;
+  const int l1 = __popcll(__ballot(lt && R.vp <= Fl)) - 1;
+  int vp, org, hl;
+  if (l1 == l0) {  // one lane holds the whole batch
+    ln = l0;
+    vp = __builtin_amdgcn_readlane(R.vp, l0);
+    org = __builtin_amdgcn_readlane(R.org, l0);
+    hl = __builtin_amdgcn_readlane(R.hl, l0);
+  } else {
+    int l = l0;
+    for (int j = l0 + 1; j <= l1; ++j)
+      l += __builtin_amdgcn_readlane(R.vp, j) <= f ? 1 : 0;
+    ln = l;
+    vp = __shfl(R.vp, l);
+    org = __shfl(R.org, l);
+    hl = __shfl(R.hl, l);
+  }
+  slot = org + wrapi((hl & 0xFFFF) + f - vp, hl >> 16);
 }
 
 // Vehicles per thread whose records stay in registers through the
 // sub-step (the tile's first kLcRes * kWave vehicles: one round of loads);
-// the rest are loaded again by each phase, kLcBatch per thread at a time.
+// the rest are loaded again by each phase, a batch per thread at a time
+// (a jammed tile holds thousands of vehicles, and each batch costs one
+// round trip to memory, so the phases with few live values per vehicle
+// take wider batches).
 constexpr int kLcRes = 2;
-constexpr int kLcBatch = 2;
+constexpr int kLcOccBatch = 6;    // occupancy: the xvf word
+constexpr int kLcDecBatch = 4;    // decisions: the hot record
+constexpr int kLcPlaceBatch = 6;  // placement: hot and cold records
 
 __device__ __forceinline__ void lc_mark_occ(const LcTile& T, const LcLat& Z,
                                             int ln, uint32_t xw) {
@@ -245,10 +289,14 @@ __device__ int lane_change_tile(const DevScen& S, int t, int nl,
   const int wi = wave_incl_scan(wpl), vi = wave_incl_scan(nv);
   const int Wt = __shfl(wi, kWave - 1), V = __shfl(vi, kWave - 1);
   if (V == 0) return 0;
+  LcLane R{0, 0, 0};
   if (i < nl) {
     T.wo[i] = wi - wpl;
     T.vp[i] = vi - nv;
     T.mv[i] = 0;
+    const int len = lmeta_len((uint32_t)T.info[i].y), hp = T.hp[i];
+    R = LcLane{vi - nv, T.info[i].x + hc_par(hp) * len,
+               hc_head(hp) | (len << 16)};
   }
   __syncthreads();
 
@@ -261,7 +309,8 @@ __device__ int lane_change_tile(const DevScen& S, int t, int nl,
     int rsl[kLcRes];
 #pragma unroll
     for (int u = 0; u < kLcRes; ++u)
-      lc_locate(T, nl, min(u * kWave + i, V - 1), rln[u], rsl[u]);
+      lc_locate(R, nl, min(u * kWave, V - 1), min(u * kWave + kWave, V) - 1,
+                min(u * kWave + i, V - 1), rln[u], rsl[u]);
 #pragma unroll
     for (int u = 0; u < kLcRes; ++u) {
       rhw[u] = hot[rsl[u]];
@@ -315,16 +364,18 @@ __device__ int lane_change_tile(const DevScen& S, int t, int nl,
 #pragma unroll
   for (int u = 0; u < kLcRes; ++u)
     if (u * kWave + i < V) lc_mark_occ(T, Z, rln[u], rhw[u].x);
-  for (int f0 = f_rest; f0 < V; f0 += kLcBatch * kWave) {
-    int ln[kLcBatch], sl[kLcBatch];
-    uint32_t xw[kLcBatch];
+  for (int f0 = f_rest; f0 < V; f0 += kLcOccBatch * kWave) {
+    int ln[kLcOccBatch], sl[kLcOccBatch];
+    uint32_t xw[kLcOccBatch];
 #pragma unroll
-    for (int u = 0; u < kLcBatch; ++u)
-      lc_locate(T, nl, min(f0 + u * kWave + i, V - 1), ln[u], sl[u]);
+    for (int u = 0; u < kLcOccBatch; ++u)
+      lc_locate(R, nl, min(f0 + u * kWave, V - 1),
+                min(f0 + u * kWave + kWave, V) - 1,
+                min(f0 + u * kWave + i, V - 1), ln[u], sl[u]);
 #pragma unroll
-    for (int u = 0; u < kLcBatch; ++u) xw[u] = hot[sl[u]].x;
+    for (int u = 0; u < kLcOccBatch; ++u) xw[u] = hot[sl[u]].x;
 #pragma unroll
-    for (int u = 0; u < kLcBatch; ++u)
+    for (int u = 0; u < kLcOccBatch; ++u)
       if (f0 + u * kWave + i < V) lc_mark_occ(T, Z, ln[u], xw[u]);
   }
   __syncthreads();
@@ -333,16 +384,18 @@ __device__ int lane_change_tile(const DevScen& S, int t, int nl,
 #pragma unroll
   for (int u = 0; u < kLcRes; ++u)
     if (u * kWave + i < V) lc_mark_move(S, T, Z, t, rln[u], rhw[u]);
-  for (int f0 = f_rest; f0 < V; f0 += kLcBatch * kWave) {
-    int ln[kLcBatch], sl[kLcBatch];
-    v2u hw[kLcBatch];
+  for (int f0 = f_rest; f0 < V; f0 += kLcDecBatch * kWave) {
+    int ln[kLcDecBatch], sl[kLcDecBatch];
+    v2u hw[kLcDecBatch];
 #pragma unroll
-    for (int u = 0; u < kLcBatch; ++u)
-      lc_locate(T, nl, min(f0 + u * kWave + i, V - 1), ln[u], sl[u]);
+    for (int u = 0; u < kLcDecBatch; ++u)
+      lc_locate(R, nl, min(f0 + u * kWave, V - 1),
+                min(f0 + u * kWave + kWave, V) - 1,
+                min(f0 + u * kWave + i, V - 1), ln[u], sl[u]);
 #pragma unroll
-    for (int u = 0; u < kLcBatch; ++u) hw[u] = hot[sl[u]];
+    for (int u = 0; u < kLcDecBatch; ++u) hw[u] = hot[sl[u]];
 #pragma unroll
-    for (int u = 0; u < kLcBatch; ++u)
+    for (int u = 0; u < kLcDecBatch; ++u)
       if (f0 + u * kWave + i < V) lc_mark_move(S, T, Z, t, ln[u], hw[u]);
   }
   __syncthreads();
@@ -387,20 +440,22 @@ __device__ int lane_change_tile(const DevScen& S, int t, int nl,
 #pragma unroll
   for (int u = 0; u < kLcRes; ++u)
     if (u * kWave + i < V) lc_place(S, T, Z, rln[u], rhw[u], rcw[u]);
-  for (int f0 = f_rest; f0 < V; f0 += kLcBatch * kWave) {
-    int ln[kLcBatch], sl[kLcBatch];
-    v2u hw[kLcBatch];
-    v2i cw[kLcBatch];
+  for (int f0 = f_rest; f0 < V; f0 += kLcPlaceBatch * kWave) {
+    int ln[kLcPlaceBatch], sl[kLcPlaceBatch];
+    v2u hw[kLcPlaceBatch];
+    v2i cw[kLcPlaceBatch];
 #pragma unroll
-    for (int u = 0; u < kLcBatch; ++u)
-      lc_locate(T, nl, min(f0 + u * kWave + i, V - 1), ln[u], sl[u]);
+    for (int u = 0; u < kLcPlaceBatch; ++u)
+      lc_locate(R, nl, min(f0 + u * kWave, V - 1),
+                min(f0 + u * kWave + kWave, V) - 1,
+                min(f0 + u * kWave + i, V - 1), ln[u], sl[u]);
 #pragma unroll
-    for (int u = 0; u < kLcBatch; ++u) {
+    for (int u = 0; u < kLcPlaceBatch; ++u) {
       hw[u] = hot[sl[u]];
       cw[u] = cold[sl[u]];
     }
 #pragma unroll
-    for (int u = 0; u < kLcBatch; ++u)
+    for (int u = 0; u < kLcPlaceBatch; ++u)
       if (f0 + u * kWave + i < V) lc_place(S, T, Z, ln[u], hw[u], cw[u]);
   }
   __syncthreads();
