@@ -51,10 +51,66 @@ __device__ __forceinline__ void load_plans(const DevScen& S, int4* s_plans) {
   if (i < S.n_plans) s_plans[i] = S.plans[i];
 }
 
-__device__ __forceinline__ unsigned long long wave_sum(unsigned long long v) {
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
-  return v;
+// Wave-wide scans and reductions by DPP (data-parallel primitives): shifts
+// within each row of 16 lanes, then broadcasts of lanes 15 and 31 into the
+// rows above them.  Each step is one vector ALU instruction, where a
+// shuffle is a round trip through the LDS crossbar.  Every lane of the
+// wavefront must be active.
+constexpr int kDppRowShr1 = 0x111, kDppRowShr2 = 0x112, kDppRowShr4 = 0x114,
+              kDppRowShr8 = 0x118, kDppWaveShr1 = 0x138,
+              kDppRowBcast15 = 0x142, kDppRowBcast31 = 0x143;
+
+// One step of a scan: x combined with the copy of x that the DPP control
+// kCtrl moves into this lane, in the rows of kRows (a lane with no source
+// row or lane combines with the identity).
+template <int kCtrl, int kRows>
+__device__ __forceinline__ int dpp_add(int x) {
+  return x + __builtin_amdgcn_update_dpp(0, x, kCtrl, kRows, 0xf, false);
+}
+template <int kCtrl, int kRows>
+__device__ __forceinline__ int dpp_min(int x) {
+  return min(x, __builtin_amdgcn_update_dpp(INT32_MAX, x, kCtrl, kRows, 0xf,
+                                            false));
+}
+
+// Inclusive prefix sum: lane i gets the sum over lanes 0..i (the wave's
+// total below 2^31).
+__device__ __forceinline__ int wave_scan(int x) {
+  x = dpp_add<kDppRowShr1, 0xf>(x);
+  x = dpp_add<kDppRowShr2, 0xf>(x);
+  x = dpp_add<kDppRowShr4, 0xf>(x);
+  x = dpp_add<kDppRowShr8, 0xf>(x);
+  x = dpp_add<kDppRowBcast15, 0xa>(x);
+  return dpp_add<kDppRowBcast31, 0xc>(x);
+}
+
+// Sum over the wavefront of values whose total is below 2^31 (every count
+// the kernels sum per wavefront: vehicles, speeds, cells of a tile), as
+// the 64-bit type of the counters it is added to.
+__device__ __forceinline__ unsigned long long wave_sum(int v) {
+  return (unsigned long long)(unsigned)__builtin_amdgcn_readlane(
+      wave_scan(v), kWave - 1);
+}
+
+// Minimum over the wavefront, in a scalar register.
+__device__ __forceinline__ int wave_min(int x) {
+  x = dpp_min<kDppRowShr1, 0xf>(x);
+  x = dpp_min<kDppRowShr2, 0xf>(x);
+  x = dpp_min<kDppRowShr4, 0xf>(x);
+  x = dpp_min<kDppRowShr8, 0xf>(x);
+  x = dpp_min<kDppRowBcast15, 0xa>(x);
+  x = dpp_min<kDppRowBcast31, 0xc>(x);
+  return __builtin_amdgcn_readlane(x, kWave - 1);
+}
+
+// Lane i gets lane i - 1's x; lane 0 gets fill.
+__device__ __forceinline__ int wave_prev(int x, int fill) {
+  return __builtin_amdgcn_update_dpp(fill, x, kDppWaveShr1, 0xf, 0xf, false);
+}
+
+// The value of the wavefront's last lane, in a scalar register
+__device__ __forceinline__ int wave_last(int x) {
+  return __builtin_amdgcn_readlane(x, kWave - 1);
 }
 
 // Orders this lane's LDS accesses before the next ones of any lane of the

@@ -119,16 +119,6 @@ __device__ int lc_decide(const DevScen& S, const uint32_t* wk, int wpl,
   return best;
 }
 
-__device__ __forceinline__ int wave_incl_scan(int v) {
-  const int i = threadIdx.x;
-#pragma unroll
-  for (int off = 1; off < kWave; off <<= 1) {
-    const int u = __shfl_up(v, off);
-    if (i >= off) v += u;
-  }
-  return v;
-}
-
 // Largest j < n with pre[j] <= f (pre ascending, pre[0] = 0 <= f, n at
 // most kMaxTileLanes), with pre[j] in *pj.  The steps are the fixed powers
 // of two below kMaxTileLanes, taken with no branch at all, so the compiler
@@ -286,8 +276,8 @@ __device__ int lane_change_tile(const DevScen& S, int t, int nl,
       k = lmeta_k(meta);
     }
   }
-  const int wi = wave_incl_scan(wpl), vi = wave_incl_scan(nv);
-  const int Wt = __shfl(wi, kWave - 1), V = __shfl(vi, kWave - 1);
+  const int wi = wave_scan(wpl), vi = wave_scan(nv);
+  const int Wt = wave_last(wi), V = wave_last(vi);
   if (V == 0) return 0;
   LcLane R{0, 0, 0};
   if (i < nl) {
@@ -334,11 +324,7 @@ __device__ int lane_change_tile(const DevScen& S, int t, int nl,
     for (int u = 0; u < kLcRes; ++u) {
       const int f = u * kWave + i;
       const int x = xvf_x(rhw[u].x);
-      int px = __shfl_up(x, 1);
-      if (u > 0) {
-        const int wrap = __shfl(prev_x, kWave - 1);
-        if (i == 0) px = wrap;
-      }
+      const int px = wave_prev(x, u > 0 ? wave_last(prev_x) : 0);
       prev_x = x;
       if (f < V) {
         const uint32_t meta = (uint32_t)T.info[rln[u]].y;
@@ -418,14 +404,14 @@ __device__ int lane_change_tile(const DevScen& S, int t, int nl,
     if (m) T.mv[ln - kk] = 1;
     moved += m;
   }
-  moved = (int)wave_sum((unsigned long long)moved);
+  moved = (int)wave_sum(moved);
   if (moved == 0) return 0;
   int carry = 0;
   for (int q0 = 0; q0 < Wt; q0 += kWave) {
     const int q = q0 + i;
-    const int c = wave_incl_scan(q < Wt ? __popc(Z.occ[q]) : 0);
+    const int c = wave_scan(q < Wt ? __popc(Z.occ[q]) : 0);
     if (q < Wt) Z.pre[q] = (uint16_t)(carry + c);
-    carry += __shfl(c, kWave - 1);
+    carry += wave_last(c);
   }
   __syncthreads();
   const bool mine = wpl > 0 && T.mv[i - k] != 0;
@@ -622,7 +608,7 @@ __global__ __launch_bounds__(kWave) void k_front(
   // kPieceCost gets more wavefronts, listed for the move kernel
   if (pieces > 1 && S.xcap > 0) {
     const unsigned long long T =
-        wave_sum((unsigned long long)(act ? cnt + kLaneCost : 0));
+        wave_sum(act ? cnt + kLaneCost : 0);
     const int np = min(pieces, (int)((T + kPieceCost - 1) / kPieceCost));
     if (i == 0) {
       int got = 0;
@@ -636,7 +622,7 @@ __global__ __launch_bounds__(kWave) void k_front(
       S.tile_np[w.w] = got + 1;
     }
   }
-  const unsigned long long n_ins = wave_sum((unsigned long long)ins);
+  const unsigned long long n_ins = wave_sum(ins);
   if (i == 0) {
     long long* ctr = S.ftile_ctr + (long long)w.w * C_N;
     if (n_ins) atomicAdd((unsigned long long*)&ctr[C_INS], n_ins);
@@ -729,13 +715,8 @@ __global__ __launch_bounds__(kWave) void k_back(
   bool act = false;
   {
     const int cost = i < nl ? hc_cnt(sum.z) + kLaneCost : 0;
-    int ci = cost;
-#pragma unroll
-    for (int off = 1; off < kWave; off <<= 1) {
-      const int y = __shfl_up(ci, off);
-      if (i >= off) ci += y;
-    }
-    const int T = __builtin_amdgcn_readfirstlane(__shfl(ci, kWave - 1));
+    const int ci = wave_scan(cost);
+    const int T = wave_last(ci);
     const int id = (int)(((long long)(ci - cost) * np) / T);
     act = i < nl && id == piece;
     if (__ballot(act) == 0ull) return;  // no run for this wavefront
@@ -761,20 +742,14 @@ __global__ __launch_bounds__(kWave) void k_back(
     s_ends[i] = make_int4(0, 0, 0, 0);
   }
   // exclusive prefix of the run's lane counts (zero outside the run)
-  int incl = cnt;
-#pragma unroll
-  for (int off = 1; off < kWave; off <<= 1) {
-    const int y = __shfl_up(incl, off);
-    if (i >= off) incl += y;
-  }
-  // uniform across the wavefront: keep it in a scalar register
-  const int total = __builtin_amdgcn_readfirstlane(__shfl(incl, kWave - 1));
+  const int incl = wave_scan(cnt);
+  const int total = wave_last(incl);  // in a scalar register
   // every lane of the tile gets its entry (lanes outside the run hold no
   // vehicles of it), so the search below only ever lands on the run's lanes
   if (i < nl) s_pre[i] = incl - cnt;
   if (i == 0) s_pre[nl] = total;
   const unsigned long long cocc =
-      wave_sum((unsigned long long)(cnt > 0 ? len : 0));
+      wave_sum(cnt > 0 ? len : 0);
   wave_lds_sync();
 
   unsigned long long sumv = 0, cross = 0, exits = 0;
@@ -885,9 +860,9 @@ __global__ __launch_bounds__(kWave) void k_back(
     lane_state[gid] = (v4i){e.x, e.y, e.z, hc};
   }
   if (refill) lane_qrec[gid] = nrec;
-  sumv = wave_sum(sumv);
-  cross = wave_sum(cross);
-  exits = wave_sum(exits);
+  sumv = wave_sum((int)sumv);
+  cross = wave_sum((int)cross);
+  exits = wave_sum((int)exits);
   const int first = __builtin_amdgcn_readfirstlane(
       __builtin_ctzll(__ballot(act)));  // the run's first lane in the tile
   ctr = (GAS unsigned long long*)gp(S.tile_ctr + (long long)(w.y + first) * C_N);

@@ -339,17 +339,12 @@ __global__ __launch_bounds__(kWave) void k_step(
     s_ends[i] = make_int4(0, 0, 0, 0);
   }
   const int cntn = cnt + n_new;
-  int incl = cntn;
-#pragma unroll
-  for (int off = 1; off < kWave; off <<= 1) {
-    const int y = __shfl_up(incl, off);
-    if (i >= off) incl += y;
-  }
-  const int total = __builtin_amdgcn_readfirstlane(__shfl(incl, kWave - 1));
+  const int incl = wave_scan(cntn);
+  const int total = wave_last(incl);  // in a scalar register
   if (i < nl) s_pre[i] = incl - cntn;
   if (i == 0) s_pre[nl] = total;
   const unsigned long long cocc =
-      wave_sum((unsigned long long)(cntn > 0 ? len : 0));
+      wave_sum(cntn > 0 ? len : 0);
   wave_lds_sync();
 
   // 3. the move, groups of kGroup x 64 vehicles from the rear: a group
@@ -448,16 +443,15 @@ __global__ __launch_bounds__(kWave) void k_step(
     }
   }
   const unsigned long long own1 = __ballot(held);
-  sumv = wave_sum(sumv);
-  cross = wave_sum(cross);
-  exits = wave_sum(exits);
-  const unsigned long long n_ins = wave_sum((unsigned long long)ins);
+  sumv = wave_sum((int)sumv);
+  cross = wave_sum((int)cross);
+  exits = wave_sum((int)exits);
+  const unsigned long long n_ins = wave_sum(ins);
   int wake1;
   if (kSkip && s_wake > t) {
     wake1 = s_wake;
   } else {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) qnx = min(qnx, __shfl_xor(qnx, off));
+    qnx = wave_min(qnx);
     wake1 = n_ins ? min(qnx, t + 1) : qnx;
   }
   if (i == 0) {
