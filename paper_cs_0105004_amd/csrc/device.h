@@ -108,6 +108,25 @@ __device__ __forceinline__ int wave_prev(int x, int fill) {
   return __builtin_amdgcn_update_dpp(fill, x, kDppWaveShr1, 0xf, 0xf, false);
 }
 
+// Lane of vehicle f in a wavefront's numbering of its tile's vehicles
+// (lanes in order, the vehicles of a lane consecutive): the largest lane j
+// whose first vehicle vp_j is at most f, where lane thread j < nl holds
+// vp_j in vp.  F and Fl are the same in every thread and bound the
+// wavefront's vehicles, F <= f <= Fl < F + kWave.  Two ballots give the
+// lanes of vehicles F and Fl; each thread then counts the lanes between
+// them that start at or below f, reading the lane threads' registers, so
+// no memory is touched.  Called by the whole wavefront.
+__device__ __forceinline__ int wave_lane_of(int vp, int nl, int F, int Fl,
+                                            int f) {
+  const bool lt = (int)threadIdx.x < nl;
+  const int l0 = __popcll(__ballot(lt && vp <= F)) - 1;
+  const int l1 = __popcll(__ballot(lt && vp <= Fl)) - 1;
+  int l = l0;
+  for (int j = l0 + 1; j <= l1; ++j)
+    l += __builtin_amdgcn_readlane(vp, j) <= f ? 1 : 0;
+  return l;
+}
+
 // The value of the wavefront's last lane, in a scalar register
 __device__ __forceinline__ int wave_last(int x) {
   return __builtin_amdgcn_readlane(x, kWave - 1);

@@ -768,14 +768,10 @@ __global__ __launch_bounds__(kWave) void k_back(
       // load sits in a divergent branch and all of them stay in flight.
 #pragma unroll
       for (int c = 0; c < kGroup; ++c) {
-        const int fr = (g0 + c) * kWave + i;
+        const int fr0 = (g0 + c) * kWave, fr = fr0 + i;
         const int f = min(fr, total - 1);
-        int lo = 0, hi = nl;
-        while (hi - lo > 1) {
-          const int mid = (lo + hi) >> 1;
-          if (s_pre[mid] <= f) lo = mid;
-          else hi = mid;
-        }
+        const int lo = wave_lane_of(incl - cnt, nl, min(fr0, total - 1),
+                                    min(fr0 + kWave - 1, total - 1), f);
         const int j = f - s_pre[lo];
         const int llen = s_len[lo], lbase = s_base[lo], lhp = s_hp[lo];
         sl[c] = rec_slot(lbase, lhp, llen, j);

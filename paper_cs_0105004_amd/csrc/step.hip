@@ -34,19 +34,15 @@ struct CrossPtrs {
 };
 
 __device__ __forceinline__ void step_load(
-    StepGroup& G, int g0, int i, int total, int nl, const int* s_pre,
-    const int* s_len, const int* s_base, const int* s_hp, GAS v2u* hot,
-    GAS uint32_t* hot_w, GAS v2i* cold) {
+    StepGroup& G, int g0, int i, int total, int nl, int vp,
+    const int* s_pre, const int* s_len, const int* s_base, const int* s_hp,
+    GAS v2u* hot, GAS uint32_t* hot_w, GAS v2i* cold) {
 #pragma unroll
   for (int c = 0; c < kGroup; ++c) {
-    const int fr = (g0 + c) * kWave + i;
+    const int fr0 = (g0 + c) * kWave, fr = fr0 + i;
     const int f = max(min(fr, total - 1), 0);
-    int lo = 0, hi = nl;
-    while (hi - lo > 1) {
-      const int mid = (lo + hi) >> 1;
-      if (s_pre[mid] <= f) lo = mid;
-      else hi = mid;
-    }
+    const int lo = wave_lane_of(vp, nl, max(min(fr0, total - 1), 0),
+                                max(min(fr0 + kWave - 1, total - 1), 0), f);
     const int j = f - s_pre[lo];
     const int llen = s_len[lo], lbase = s_base[lo], lhp = s_hp[lo];
     G.sl[c] = rec_slot(lbase, lhp, llen, j);
@@ -357,8 +353,8 @@ __global__ __launch_bounds__(kWave) void k_step(
   // (one pass with no vehicle still decides the winners)
   for (int gr = ((nchunk - 1) / kGroup) * kGroup; gr >= 0; gr -= kGroup) {
     StepGroup G;
-    step_load(G, gr, i, total, nl, s_pre, s_len, s_base, s_hp, hot, hot_w,
-              cold);
+    step_load(G, gr, i, total, nl, incl - cntn, s_pre, s_len, s_base, s_hp,
+              hot, hot_w, cold);
     if (first) {
       first = false;
       // the arrivals' records go to LDS; the inserting lane takes the queue
