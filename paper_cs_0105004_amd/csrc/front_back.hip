@@ -81,15 +81,23 @@ __device__ __forceinline__ int lc_behind(const uint32_t* w, int wpl, int x,
 }
 
 // Target lane of the vehicle at cell x of lane k, or -1; wk: lane k's words
-__device__ int lc_decide(const DevScen& S, const uint32_t* wk, int wpl,
+// The scenario's lane-change parameters, read from the descriptor once per
+// tile (uniform values, kept in scalar registers)
+struct LcParams {
+  int vmax, desp;
+  uint64_t thr;
+  uint32_t key0, key1;
+};
+
+__device__ int lc_decide(const LcParams& P, const uint32_t* wk, int wpl,
                          int len, int lanes, int k, int x, int v, uint32_t fl,
                          int id, int t) {
-  const int vmax = S.vmax;
+  const int vmax = P.vmax;
   const int lo = fl_lo(fl), hi = fl_hi(fl);
   if (k < lo || k > hi) {  // mandatory: one lane toward the turn lanes
     const int m = k < lo ? k + 1 : k - 1;
     const uint32_t* wm = wk + (m - k) * wpl;
-    const int need = min(vmax, (len - 1 - x) / S.lc_desp);
+    const int need = min(vmax, (len - 1 - x) / P.desp);
     if (!lane_bit(wm, x) && lc_behind(wm, wpl, x, vmax) >= need) return m;
     return -1;
   }
@@ -112,9 +120,9 @@ __device__ int lc_decide(const DevScen& S, const uint32_t* wk, int wpl,
   }
   if (best < 0) return -1;
   // a threshold of 2^32 takes every draw, which is then not made
-  if (S.lc_thr < (1ull << 32) &&
-      (uint64_t)veh_draw((uint32_t)id, (uint32_t)t, 0u, S.key0, S.key1) >=
-          S.lc_thr)
+  if (P.thr < (1ull << 32) &&
+      (uint64_t)veh_draw((uint32_t)id, (uint32_t)t, 0u, P.key0, P.key1) >=
+          P.thr)
     return -1;
   return best;
 }
@@ -206,14 +214,14 @@ __device__ __forceinline__ void lc_mark_occ(const LcTile& T, const LcLat& Z,
   atomicOr(&Z.occ[T.wo[ln] + (x >> 5)], 1u << (x & 31));
 }
 
-__device__ __forceinline__ void lc_mark_move(const DevScen& S, const LcTile& T,
+__device__ __forceinline__ void lc_mark_move(const LcParams& P, const LcTile& T,
                                              const LcLat& Z, int t, int ln,
                                              v2u hw) {
   const uint32_t meta = (uint32_t)T.info[ln].y;
   const int len = lmeta_len(meta), k = lmeta_k(meta);
   const int wl = (len + 31) >> 5, q0 = T.wo[ln];
   const int x = xvf_x(hw.x);
-  const int d = lc_decide(S, Z.occ + q0, wl, len, lmeta_lanes(meta), k, x,
+  const int d = lc_decide(P, Z.occ + q0, wl, len, lmeta_lanes(meta), k, x,
                           xvf_v(hw.x), xvf_fl(hw.x), (int)hw.y, t);
   if (d < 0) return;
   atomicOr(d > k ? &Z.rgt[q0 + (x >> 5)] : &Z.lft[q0 + (x >> 5)],
@@ -222,7 +230,8 @@ __device__ __forceinline__ void lc_mark_move(const DevScen& S, const LcTile& T,
 
 // Writes the vehicle's records at its place in its lane after the sub-step
 // (links with a move only).
-__device__ __forceinline__ void lc_place(const DevScen& S, const LcTile& T,
+__device__ __forceinline__ void lc_place(GAS v2u* hot, GAS v2i* cold,
+                                         uint32_t* err, const LcTile& T,
                                          const LcLat& Z, int ln, v2u hw,
                                          v2i cw) {
   const uint32_t meta = (uint32_t)T.info[ln].y;
@@ -240,13 +249,11 @@ __device__ __forceinline__ void lc_place(const DevScen& S, const LcTile& T,
   const int j = __popc(b == 31 ? 0u : Z.occ[qd] >> (b + 1)) +
                 (int)(uint16_t)(Z.pre[T.wo[lnd] + wl - 1] - Z.pre[qd]);
   if (j >= len) {  // never: a lane holds at most len vehicles
-    atomicOr(S.err, SIM_DEVERR_LANE_FULL);
+    atomicOr(err, SIM_DEVERR_LANE_FULL);
     return;
   }
   const int npar = 1 - hc_par(T.hp[ln]);
   const int dst = T.info[lnd].x + npar * len + j;
-  GAS v2u* hot = gpv<v2u>(S.hot);
-  GAS v2i* cold = gpv<v2i>(S.cold);
   hot[dst] = hw;
   cold[dst] = cw;
   if (j == 0) {
@@ -267,6 +274,8 @@ __device__ int lane_change_tile(const DevScen& S, int t, int nl,
   const int i = threadIdx.x;
   GAS v2u* hot = gpv<v2u>(S.hot);
   GAS v2i* cold = gpv<v2i>(S.cold);
+  uint32_t* const err = S.err;
+  const LcParams P{S.vmax, S.lc_desp, S.lc_thr, S.key0, S.key1};
   int wpl = 0, nv = 0, k = 0;
   if (i < nl) {
     const uint32_t meta = (uint32_t)T.info[i].y;
@@ -317,7 +326,7 @@ __device__ int lane_change_tile(const DevScen& S, int t, int nl,
   // changes nothing and the lattice is never built.  Vehicles past the
   // first kLcRes * kWave count as qualifying.
   {
-    const int vmax = S.vmax;
+    const int vmax = P.vmax;
     bool want = V > f_rest;
     int prev_x = 0;
 #pragma unroll
@@ -369,7 +378,7 @@ __device__ int lane_change_tile(const DevScen& S, int t, int nl,
   // decisions
 #pragma unroll
   for (int u = 0; u < kLcRes; ++u)
-    if (u * kWave + i < V) lc_mark_move(S, T, Z, t, rln[u], rhw[u]);
+    if (u * kWave + i < V) lc_mark_move(P, T, Z, t, rln[u], rhw[u]);
   for (int f0 = f_rest; f0 < V; f0 += kLcDecBatch * kWave) {
     int ln[kLcDecBatch], sl[kLcDecBatch];
     v2u hw[kLcDecBatch];
@@ -382,7 +391,7 @@ __device__ int lane_change_tile(const DevScen& S, int t, int nl,
     for (int u = 0; u < kLcDecBatch; ++u) hw[u] = hot[sl[u]];
 #pragma unroll
     for (int u = 0; u < kLcDecBatch; ++u)
-      if (f0 + u * kWave + i < V) lc_mark_move(S, T, Z, t, ln[u], hw[u]);
+      if (f0 + u * kWave + i < V) lc_mark_move(P, T, Z, t, ln[u], hw[u]);
   }
   __syncthreads();
 
@@ -425,7 +434,8 @@ __device__ int lane_change_tile(const DevScen& S, int t, int nl,
   // rebuild the lanes of the links that moved, lead first
 #pragma unroll
   for (int u = 0; u < kLcRes; ++u)
-    if (u * kWave + i < V) lc_place(S, T, Z, rln[u], rhw[u], rcw[u]);
+    if (u * kWave + i < V)
+      lc_place(hot, cold, err, T, Z, rln[u], rhw[u], rcw[u]);
   for (int f0 = f_rest; f0 < V; f0 += kLcPlaceBatch * kWave) {
     int ln[kLcPlaceBatch], sl[kLcPlaceBatch];
     v2u hw[kLcPlaceBatch];
@@ -442,7 +452,8 @@ __device__ int lane_change_tile(const DevScen& S, int t, int nl,
     }
 #pragma unroll
     for (int u = 0; u < kLcPlaceBatch; ++u)
-      if (f0 + u * kWave + i < V) lc_place(S, T, Z, ln[u], hw[u], cw[u]);
+      if (f0 + u * kWave + i < V)
+        lc_place(hot, cold, err, T, Z, ln[u], hw[u], cw[u]);
   }
   __syncthreads();
   if (mine) T.hp[i] = hc_make(0, 1 - hc_par(T.hp[i]), 0);
@@ -484,6 +495,13 @@ __global__ __launch_bounds__(kWave) void k_front(
   // the lane-change pass reaches the records through the descriptor too
   GAS v2u* hot = gpv<v2u>(S.hot);
   GAS v2i* cold = gpv<v2i>(S.cold);
+  // what the end of the kernel writes through, read with the rest of the
+  // descriptor rather than one field after another at the end
+  const int xcap = S.xcap;
+  int* const xcount = S.xcount;
+  int4* const xlist = S.xlist;
+  int* const tile_np = S.tile_np;
+  long long* const ftile_ctr = S.ftile_ctr;
   const int i = threadIdx.x;
   const int nl = w.z;
   const bool act = i < nl;
@@ -606,25 +624,25 @@ __global__ __launch_bounds__(kWave) void k_front(
   }
   // runs of this tile for the move sub-step: a tile heavier than
   // kPieceCost gets more wavefronts, listed for the move kernel
-  if (pieces > 1 && S.xcap > 0) {
+  if (pieces > 1 && xcap > 0) {
     const unsigned long long T =
         wave_sum(act ? cnt + kLaneCost : 0);
     const int np = min(pieces, (int)((T + kPieceCost - 1) / kPieceCost));
     if (i == 0) {
       int got = 0;
       if (np > 1) {
-        const int xb = atomicAdd(&S.xcount[t & 1], np - 1);
-        got = max(0, min(S.xcap - xb, np - 1));
+        const int xb = atomicAdd(&xcount[t & 1], np - 1);
+        got = max(0, min(xcap - xb, np - 1));
         for (int r = 0; r < got; ++r)
-          S.xlist[xb + r] =
+          xlist[xb + r] =
               make_int4(w.y, w.z | ((r + 1) << 8) | ((got + 1) << 16), w.w, 0);
       }
-      S.tile_np[w.w] = got + 1;
+      tile_np[w.w] = got + 1;
     }
   }
   const unsigned long long n_ins = wave_sum(ins);
   if (i == 0) {
-    long long* ctr = S.ftile_ctr + (long long)w.w * C_N;
+    long long* ctr = ftile_ctr + (long long)w.w * C_N;
     if (n_ins) atomicAdd((unsigned long long*)&ctr[C_INS], n_ins);
     if (lc_moves) atomicAdd((unsigned long long*)&ctr[C_LC],
                             (unsigned long long)lc_moves);
