@@ -138,29 +138,22 @@ def family_of(kinds) -> str:
 # this digest (of the kernel's family) and for exactly that window and tile
 # shape; any other run reports null.
 MEASURED_TRAFFIC = {
-    "e0657611fe69b54c": {  # step.hip family
+    "506c4769d0d659fe": {  # step.hip family
         "portland": [
             # k_step<false, false>, the default 16-lane / 1,024-cell tiles,
-            # window [1800, 1820): FETCH 3284.4 KiB x 2.0 + WRITE 2272.0 KiB
+            # window [1800, 1820): FETCH 3277.7 KiB x 2.0 + WRITE 2272.0 KiB
             {"window": (1800, 20), "tiles": (16, 1024),
-             "bytes_per_launch": 8840.8 * 1024},
-            # window [1800, 1900): FETCH 3161.5 x 2.0 + WRITE 2175.0
+             "bytes_per_launch": 8827.4 * 1024},
+            # window [1800, 1900): FETCH 3154.7 x 2.0 + WRITE 2175.0
             {"window": (1800, 100), "tiles": (16, 1024),
-             "bytes_per_launch": 8498.0 * 1024},
-            # k_step<false, false>, 16-lane / 2,048-cell tiles, window
-            # [1800, 1820): FETCH 3013.6 KiB x 2.0 + WRITE 1940.9 KiB x 1.0
-            {"window": (1800, 20), "tiles": (16, 2048),
-             "bytes_per_launch": 7968.1 * 1024},
-            # window [1800, 1900): FETCH 2860.0 x 2.0 + WRITE 1844.4
-            {"window": (1800, 100), "tiles": (16, 2048),
-             "bytes_per_launch": 7564.4 * 1024},
+             "bytes_per_launch": 8484.4 * 1024},
         ],
         "batched": [
             # k_step<true, false>, 64 replications, 64-lane / 12,288-cell
-            # tiles, window [1800, 1900): FETCH 52438.9 KiB x 2.0 + WRITE
-            # 34041.3 KiB x 1.0
+            # tiles, window [1800, 1900): FETCH 52426.4 KiB x 2.0 + WRITE
+            # 34034.4 KiB x 1.0
             {"window": (1800, 100), "tiles": (64, 12288),
-             "bytes_per_launch": 138919.1 * 1024},
+             "bytes_per_launch": 138887.2 * 1024},
         ],
     },
 }
