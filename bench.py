@@ -66,6 +66,16 @@ def make_workload(name: str):
                "nodes": scen.n_nodes, "lanes": int(scen.link_lanes.sum()),
                "vehicles": scen.n_veh, "horizon_steps": scen.T, "vmax": 5,
                "p": 0.2, "lane_change": True, "turn_lanes": True}
+    elif name == "large_quarter":
+        # the same generator at a quarter of the grid and the demand: the
+        # same kernels and congestion pattern, for counter passes that the
+        # full-size network does not complete under the profiler
+        scen = S.large_network(scale=0.25)
+        cfg = {"workload": "large_grid_quarter_50k_links",
+               "links": scen.n_links, "nodes": scen.n_nodes,
+               "lanes": int(scen.link_lanes.sum()), "vehicles": scen.n_veh,
+               "horizon_steps": scen.T, "vmax": 5, "p": 0.2,
+               "lane_change": True, "turn_lanes": True}
     elif name == "ring":
         scen = S.ring()
         cfg = {"workload": "ring_1000_cells", "vehicles": 150,
@@ -154,6 +164,15 @@ MEASURED_TRAFFIC = {
             # 34034.4 KiB x 1.0
             {"window": (1800, 100), "tiles": (64, 12288),
              "bytes_per_launch": 138887.2 * 1024},
+        ],
+    },
+    "b2ec0e9185779a06": {  # front_back.hip family (lane change + move)
+        "large_quarter": [
+            # per step, default 32-lane / 4,096-cell tiles, window
+            # [7100, 7200): k_front FETCH 7783.5 KiB x 2.0 + WRITE 2498.3
+            # KiB; k_back FETCH 6795.4 x 2.0 + WRITE 5631.4
+            {"window": (7100, 100), "tiles": (32, 4096),
+             "bytes_per_launch": 37287.5 * 1024},
         ],
     },
 }
@@ -801,6 +820,7 @@ def counter_pass(args):
         ctx.load(k, sc)
     T = scens[0].T
     best, t_peak, t = -1, 0, 0
+    log("counter pass: locating the demand peak")
     while t < T:
         m = min(50, T - t)
         ctx.step(slots, m)
@@ -808,11 +828,21 @@ def counter_pass(args):
         a = sum(ctx.stats(k)["n_active"] for k in slots)
         if a > best:
             best, t_peak = a, t
+        if t % 1000 == 0:
+            log(f"counter pass: t = {t}")
     t0 = min(max(t_peak, K), T - K)
     for k, sc in enumerate(scens):
         ctx.load(k, sc)
-    ctx.step(slots, t0)
+    log(f"counter pass: advancing to t = {t0}")
+    done = 0
+    while done < t0:
+        m = min(1000, t0 - done)
+        ctx.step(slots, m)
+        done += m
+        ctx.stats(0)
+        log(f"counter pass: t = {done}")
     st_a = [ctx.stats(k) for k in slots]
+    log(f"counter pass: the window [{t0}, {t0 + K})")
     ctx.step(slots, K)
     st_b = [ctx.stats(k) for k in slots]
     win = {c: sum(b[c] - a[c] for a, b in zip(st_a, st_b))
@@ -969,7 +999,7 @@ def bench_single(args):
     # the tile shape the traffic was measured with: the library's defaults
     # (16 lanes / 1,024 cells for one-kernel scenarios, 32 / 4,096 with lane
     # changes) unless given
-    lc = args.workload == "large"
+    lc = args.workload in ("large", "large_quarter")
     tiles = (args.tile_lanes or (32 if lc else 16),
              args.tile_cells or (4096 if lc else 1024))
     roof = roofline_from(kt, [win], region_ms, workload=args.workload,
@@ -1000,10 +1030,11 @@ def bench_single(args):
         "roofline": roof,
     }
     if not args.no_cpu_baseline:
-        if args.workload == "large":
+        if args.workload in ("large", "large_quarter"):
             # the oracle would need most of an hour to reach the peak of the
-            # 200,000-link network: it is timed on its first steps instead,
-            # and the GPU is checked against it where it stopped
+            # 200,000-link network (a quarter of that for the quarter-size
+            # one): it is timed on its first steps instead, and the GPU is
+            # checked against it where it stopped
             log(f"bench: oracle sample ({args.cpu_seconds:.0f} s budget)")
             out["cpu_baseline"], ost = cpu_baseline(scen, args.cpu_seconds)
             log(f"bench: GPU against the oracle at step {ost['t']}")
