@@ -38,6 +38,13 @@ void* step_kernel(bool batched, bool skip);
 void* front_kernel(bool batched);
 void* back_kernel(bool batched);
 void* advance_kernel();
+// order(descs, work, n, snap): each XCD's positions of the two-kernel
+// work list of n items, the tile that took longest in the front kernel
+// since the last ordering first; snap[n] holds each position's cycle count
+// at the last ordering.  One workgroup of kOrderThreads per XCD, for at
+// most kOrderMax positions per XCD (8 * kOrderMax items).
+void* order_kernel();
+constexpr int kOrderThreads = 1024, kOrderMax = 2048;
 constexpr int kFrontThreads = kWave, kBackThreadsPerPiece = kWave;
 constexpr int kLcBytesPerWord = 14;
 // A link has at most 4 lanes of at most 32767 cells (1024 words each), and a

@@ -243,9 +243,67 @@ __global__ void k_export_set(const DevScen* d, ExportBufs o, int ring) {
   }
 }
 
+// Each XCD's share of the lane-change kernel's work list, longest-running
+// tile first.  The dispatcher deals list positions x, x + 8, x + 16, ... to
+// XCD x, and a launch with more tiles than fit on the device at once ends
+// late when a heavy tile starts late.  The heavy tiles of a congested
+// network move with the congestion, so the order follows what each tile
+// took in the front kernel since the list was last ordered (its cycle
+// counter less the count snap holds for its position), not a fixed
+// estimate.  Workgroup x sorts its positions in LDS (bitonic, descending;
+// ties keep their order) and writes the items and their current counts
+// back.  Which tile runs where changes no result.
+__global__ __launch_bounds__(kOrderThreads) void k_order(
+    const DevScen* __restrict__ descs, int4* __restrict__ work, int n,
+    long long* __restrict__ snap) {
+  __shared__ unsigned long long s_key[kOrderMax];
+  __shared__ int4 s_item[kOrderMax];
+  const int x = blockIdx.x;
+  const int m = n > x ? (n - x + 7) / 8 : 0;  // this XCD's positions
+  if (m > kOrderMax) return;  // (the host launches it only below that)
+  auto cycles = [&](int4 w) {
+    return descs[w.x].ftile_ctr[(long long)w.w * C_N + C_CYCLES];
+  };
+  for (int k = threadIdx.x; k < kOrderMax; k += kOrderThreads) {
+    unsigned long long key = 0;  // padding sorts last
+    if (k < m) {
+      const int4 w = work[x + 8 * k];
+      const long long d = cycles(w) - snap[x + 8 * k];
+      const unsigned long long dt =
+          d <= 0 ? 0ull : (d >= 0xFFFFFFFFll ? 0xFFFFFFFFull
+                                            : (unsigned long long)d);
+      key = (dt << 32) | (unsigned long long)(kOrderMax - k);
+      s_item[k] = w;
+    }
+    s_key[k] = key;
+  }
+  for (int size = 2; size <= kOrderMax; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      __syncthreads();
+      for (int t = threadIdx.x; t < kOrderMax / 2; t += kOrderThreads) {
+        const int lo = 2 * t - (t & (stride - 1)), hi = lo + stride;
+        const bool desc = (lo & size) == 0;
+        const unsigned long long a = s_key[lo], b = s_key[hi];
+        if (desc ? a < b : a > b) {
+          s_key[lo] = b;
+          s_key[hi] = a;
+        }
+      }
+    }
+  }
+  __syncthreads();
+  for (int j = threadIdx.x; j < m; j += kOrderThreads) {
+    const int k = kOrderMax - (int)(s_key[j] & 0xFFFFFFFFull);
+    const int4 w = s_item[k];
+    work[x + 8 * j] = w;
+    snap[x + 8 * j] = cycles(w);
+  }
+}
+
 // ---- launchers -------------------------------------------------------------
 
 void* advance_kernel() { return reinterpret_cast<void*>(&k_advance); }
+void* order_kernel() { return reinterpret_cast<void*>(&k_order); }
 
 // Each launcher first clears any error left by earlier runtime calls of this
 // thread, so that the status it returns is the launch's own.

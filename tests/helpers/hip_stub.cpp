@@ -122,6 +122,7 @@ void* step_kernel(bool, bool) { return &kernel_token; }
 void* front_kernel(bool) { return &kernel_token; }
 void* back_kernel(bool) { return &kernel_token; }
 void* advance_kernel() { return &kernel_token; }
+void* order_kernel() { return &kernel_token; }
 hipError_t launch_advance(DevScen*, const int*, int, int, hipStream_t) {
   return hipSuccess;
 }
