@@ -355,11 +355,30 @@ __device__ int lane_change_tile(const DevScen& S, int t, int nl,
   }
   __syncthreads();
 
-  // occupancy
+  // occupancy.  The first reload batch keeps its vehicles' lanes and xvf
+  // words in registers for the decisions, which need nothing else of a
+  // vehicle when no draw is taken (a lane-change threshold of 2^32).
 #pragma unroll
   for (int u = 0; u < kLcRes; ++u)
     if (u * kWave + i < V) lc_mark_occ(T, Z, rln[u], rhw[u].x);
-  for (int f0 = f_rest; f0 < V; f0 += kLcOccBatch * kWave) {
+  const bool keep = P.thr >= (1ull << 32);
+  int kln[kLcOccBatch];
+  uint32_t kxw[kLcOccBatch];
+  if (V > f_rest) {
+    int sl[kLcOccBatch];
+#pragma unroll
+    for (int u = 0; u < kLcOccBatch; ++u)
+      lc_locate(R, nl, min(f_rest + u * kWave, V - 1),
+                min(f_rest + u * kWave + kWave, V) - 1,
+                min(f_rest + u * kWave + i, V - 1), kln[u], sl[u]);
+#pragma unroll
+    for (int u = 0; u < kLcOccBatch; ++u) kxw[u] = hot[sl[u]].x;
+#pragma unroll
+    for (int u = 0; u < kLcOccBatch; ++u)
+      if (f_rest + u * kWave + i < V) lc_mark_occ(T, Z, kln[u], kxw[u]);
+  }
+  for (int f0 = f_rest + kLcOccBatch * kWave; f0 < V;
+       f0 += kLcOccBatch * kWave) {
     int ln[kLcOccBatch], sl[kLcOccBatch];
     uint32_t xw[kLcOccBatch];
 #pragma unroll
@@ -379,7 +398,15 @@ __device__ int lane_change_tile(const DevScen& S, int t, int nl,
 #pragma unroll
   for (int u = 0; u < kLcRes; ++u)
     if (u * kWave + i < V) lc_mark_move(P, T, Z, t, rln[u], rhw[u]);
-  for (int f0 = f_rest; f0 < V; f0 += kLcDecBatch * kWave) {
+  int f_dec = f_rest;  // first vehicle the loop below reloads
+  if (keep && V > f_rest) {
+#pragma unroll
+    for (int u = 0; u < kLcOccBatch; ++u)
+      if (f_rest + u * kWave + i < V)
+        lc_mark_move(P, T, Z, t, kln[u], (v2u){kxw[u], 0u});
+    f_dec = f_rest + kLcOccBatch * kWave;
+  }
+  for (int f0 = f_dec; f0 < V; f0 += kLcDecBatch * kWave) {
     int ln[kLcDecBatch], sl[kLcDecBatch];
     v2u hw[kLcDecBatch];
 #pragma unroll

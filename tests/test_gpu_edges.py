@@ -81,13 +81,16 @@ def test_lane_changes_on_the_longest_links(tile_cells):
     ctx.close()
 
 
-@pytest.mark.parametrize("tile_lanes", [64, 8])
-def test_lane_changes_in_a_jam(tile_lanes):
+@pytest.mark.parametrize("tile_lanes,p_lc", [(64, "1"), (8, "1"), (64, "0.6")])
+def test_lane_changes_in_a_jam(tile_lanes, p_lc):
     # every vehicle released at t = 0 onto short 2-4 lane links: many
-    # vehicles per tile (several batches of the lane-change pass)
+    # vehicles per tile (several batches of the lane-change pass); with
+    # p_lc < 1 every discretionary change takes a draw, which needs the
+    # vehicle's id from its record in every batch
     scen = S.grid_scenario(4, 5, 40, 6000, T=200, depart_max=0, seed=18,
                            lanes_range=(2, 4),
                            flags=S.FLAG_LANE_CHANGE | S.FLAG_TURN_LANES)
+    scen.lc_thr = S.prob_threshold(p_lc)
     ctx = _ctx(1, tile_lanes=tile_lanes, tile_cells=65536)
     o = run_side_by_side(ctx, 0, scen, 200, every=20, full_at=(1, 2, 100))
     assert o.stats()["lane_changes"] > 0
