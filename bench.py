@@ -166,13 +166,13 @@ MEASURED_TRAFFIC = {
              "bytes_per_launch": 138887.2 * 1024},
         ],
     },
-    "b2ec0e9185779a06": {  # front_back.hip family (lane change + move)
+    "504af3acdc7ae0ac": {  # front_back.hip family (lane change + move)
         "large_quarter": [
             # per step, default 32-lane / 4,096-cell tiles, window
-            # [7100, 7200): k_front FETCH 7783.5 KiB x 2.0 + WRITE 2498.3
-            # KiB; k_back FETCH 6795.4 x 2.0 + WRITE 5631.4
+            # [7100, 7200): k_front FETCH 7863.3 KiB x 2.0 + WRITE 2498.6
+            # KiB; k_back FETCH 6798.9 x 2.0 + WRITE 5631.5
             {"window": (7100, 100), "tiles": (32, 4096),
-             "bytes_per_launch": 37287.5 * 1024},
+             "bytes_per_launch": 37454.5 * 1024},
         ],
     },
 }
