@@ -701,14 +701,19 @@ __global__ __launch_bounds__(kWave) void k_back(
   // wavefront can leave early)
   if (!kBatched && blockIdx.x == 0 && threadIdx.x == 0 && descs[slot].xcap > 0)
     descs[slot].xcount[(descs[slot].t + step + 1) & 1] = 0;
+  // A single slot's extra wavefronts of heavy tiles take the first xcap
+  // blocks, so that they start with the first tiles (the heaviest, in a
+  // list ordered by measured time) instead of after every tile; the tiles
+  // follow, xcap (a multiple of 8) keeping each on its XCD.
+  const int xcap = kBatched ? 0 : descs[slot].xcap;
   int4 w;
   int piece = 0, np = 1;
-  if ((int)blockIdx.x < n_work) {
-    w = work[blockIdx.x];
-    if (!kBatched && descs[slot].xcap > 0) np = descs[slot].tile_np[w.w];
+  if ((int)blockIdx.x >= xcap) {
+    w = work[blockIdx.x - xcap];
+    if (xcap > 0) np = descs[slot].tile_np[w.w];
   } else {  // an extra wavefront of a heavy tile (single slot only)
     const DevScen& S1 = descs[slot];
-    const int e = (int)blockIdx.x - n_work;
+    const int e = (int)blockIdx.x;
     const int t1 = S1.t + step;
     if (e >= min(S1.xcount[t1 & 1], S1.xcap)) return;
     const int4 x = S1.xlist[e];

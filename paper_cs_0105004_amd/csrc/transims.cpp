@@ -175,9 +175,12 @@ constexpr int32_t kMaxGraphSteps = 4096;  // steps per HIP graph
 // own; shorter ones are launched kernel by kernel
 constexpr int32_t kMinRestGraph = 8;
 
-// entries of the list of extra move wavefronts for `tiles` tiles
+// entries of the list of extra move wavefronts for `tiles` tiles, a
+// multiple of 8: the move kernel gives them its first blocks, and the
+// tiles after them keep their XCD (block mod 8)
 int64_t extra_cap(int64_t tiles, int pieces) {
-  return std::min<int64_t>(tiles * std::max(pieces - 1, 0), kExtraRunsMax);
+  const int64_t n = tiles * std::max(pieces - 1, 0);
+  return std::min<int64_t>((n + 7) / 8 * 8, kExtraRunsMax);
 }
 
 // device arrays of the network part; pointers are null when measuring
