@@ -166,13 +166,13 @@ MEASURED_TRAFFIC = {
              "bytes_per_launch": 138887.2 * 1024},
         ],
     },
-    "504af3acdc7ae0ac": {  # front_back.hip family (lane change + move)
+    "00c4255505f63b72": {  # front_back.hip family (lane change + move)
         "large_quarter": [
             # per step, default 32-lane / 4,096-cell tiles, window
-            # [7100, 7200): k_front FETCH 7863.3 KiB x 2.0 + WRITE 2498.6
-            # KiB; k_back FETCH 6798.9 x 2.0 + WRITE 5631.5
+            # [7100, 7200): k_front FETCH 7863.3 KiB x 2.0 + WRITE 2498.5
+            # KiB; k_back FETCH 6798.5 x 2.0 + WRITE 5631.5
             {"window": (7100, 100), "tiles": (32, 4096),
-             "bytes_per_launch": 37454.5 * 1024},
+             "bytes_per_launch": 37453.6 * 1024},
         ],
     },
 }
