@@ -148,22 +148,22 @@ def family_of(kinds) -> str:
 # this digest (of the kernel's family) and for exactly that window and tile
 # shape; any other run reports null.
 MEASURED_TRAFFIC = {
-    "506c4769d0d659fe": {  # step.hip family
+    "800401fd3b3c1d68": {  # step.hip family
         "portland": [
             # k_step<false, false>, the default 16-lane / 1,024-cell tiles,
-            # window [1800, 1820): FETCH 3277.7 KiB x 2.0 + WRITE 2272.0 KiB
+            # window [1800, 1820): FETCH 3277.6 KiB x 2.0 + WRITE 2272.0 KiB
             {"window": (1800, 20), "tiles": (16, 1024),
-             "bytes_per_launch": 8827.4 * 1024},
+             "bytes_per_launch": 8827.2 * 1024},
             # window [1800, 1900): FETCH 3154.7 x 2.0 + WRITE 2175.0
             {"window": (1800, 100), "tiles": (16, 1024),
              "bytes_per_launch": 8484.4 * 1024},
         ],
         "batched": [
             # k_step<true, false>, 64 replications, 64-lane / 12,288-cell
-            # tiles, window [1800, 1900): FETCH 52426.4 KiB x 2.0 + WRITE
-            # 34034.4 KiB x 1.0
+            # tiles, window [1800, 1900): FETCH 52428.6 KiB x 2.0 + WRITE
+            # 34034.8 KiB x 1.0
             {"window": (1800, 100), "tiles": (64, 12288),
-             "bytes_per_launch": 138887.2 * 1024},
+             "bytes_per_launch": 138892.0 * 1024},
         ],
     },
     "00c4255505f63b72": {  # front_back.hip family (lane change + move)
