@@ -89,7 +89,11 @@ typedef struct {
                            by one.  Steps left after whole replays (or a
                            call of fewer steps) run as a graph of their own
                            when there are at least 8 of them; that graph is
-                           kept while later calls leave the same number   */
+                           kept while later calls leave the same number.
+                           With lane changes and more tiles than are
+                           resident at once, each replay first reorders the
+                           tiles by their measured lane-change time, which
+                           changes no result                               */
   int32_t step_mode;    /* 0 = one kernel per step for scenarios without
                            lane changes whose links all have >= 2*vmax
                            cells, two kernels (lane-change / move sub-step)
