@@ -151,3 +151,30 @@ def test_batched_lane_change_slots_with_different_lattices():
         assert_same_state(ctx.state(k), o.state(), f"slot {k}")
         assert o.stats()["lane_changes"] > 0
     ctx.close()
+
+
+def test_lane_change_tiles_reordered_between_graph_replays():
+    # one link per tile, three lane-changing slots in one list: between
+    # 6,144 and 16,384 tiles, so every graph replay first reorders each
+    # XCD's tiles by the time each took in the lane-change kernel since the
+    # replay before (entries of different slots mixed); the order changes
+    # no result
+    flags = S.FLAG_LANE_CHANGE | S.FLAG_TURN_LANES
+    scens = [S.portland_like(scale=sc, T=200, depart_max=100, seed=sd,
+                             flags=flags)
+             for sc, sd in ((0.15, 62), (0.1, 61), (0.15, 63))]
+    from paper_cs_0105004_amd.sim import Context
+    ctx = Context(max_slots=len(scens), tile_lanes=1, tile_cells=64,
+                  graph_steps=32)
+    for k, sc in enumerate(scens):
+        ctx.load(k, sc)
+    ctx.step([0, 1, 2], 192)  # six replays
+    n_tiles = sum(ctx.tiling(k)["n_tiles"] for k in range(len(scens)))
+    assert 6144 < n_tiles <= 8 * 2048, n_tiles
+    for k, sc in enumerate(scens):
+        o = oracle.OracleSim(sc)
+        o.step(192)
+        assert_same_stats(ctx.stats(k), o.stats(), f"slot {k}")
+        assert_same_state(ctx.state(k), o.state(), f"slot {k}")
+        assert o.stats()["lane_changes"] > 0
+    ctx.close()
