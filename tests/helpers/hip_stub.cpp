@@ -68,6 +68,21 @@ hipError_t hipEventElapsedTime(float* ms, hipEvent_t, hipEvent_t) {
 
 // Graphs: handles that stand for nothing; a launch runs no kernel.
 static int graph_token;
+// The tile-ordering kernel has a token of its own, so that the nodes that
+// launch it can be counted: how many since the last query, and the grid
+// and list length (its third argument) of the last one.
+static int order_token;
+static int order_nodes = 0, order_last_n = -1, order_last_grid = 0;
+
+int stub_order_nodes(int* last_n, int* last_grid) {
+  const int k = order_nodes;
+  *last_n = order_last_n;
+  *last_grid = order_last_grid;
+  order_nodes = 0;
+  order_last_n = -1;
+  order_last_grid = 0;
+  return k;
+}
 
 hipError_t hipGraphCreate(hipGraph_t* pGraph, unsigned int) {
   *pGraph = reinterpret_cast<hipGraph_t>(&graph_token);
@@ -78,7 +93,12 @@ hipError_t hipGraphDestroy(hipGraph_t) { return hipSuccess; }
 
 hipError_t hipGraphAddKernelNode(hipGraphNode_t* pGraphNode, hipGraph_t,
                                  const hipGraphNode_t*, size_t,
-                                 const hipKernelNodeParams*) {
+                                 const hipKernelNodeParams* p) {
+  if (p && p->func == &order_token) {
+    ++order_nodes;
+    order_last_n = *static_cast<const int*>(p->kernelParams[2]);
+    order_last_grid = (int)p->gridDim.x;
+  }
   *pGraphNode = reinterpret_cast<hipGraphNode_t>(&graph_token);
   return hipSuccess;
 }
@@ -122,7 +142,7 @@ void* step_kernel(bool, bool) { return &kernel_token; }
 void* front_kernel(bool) { return &kernel_token; }
 void* back_kernel(bool) { return &kernel_token; }
 void* advance_kernel() { return &kernel_token; }
-void* order_kernel() { return &kernel_token; }
+void* order_kernel() { return &order_token; }
 hipError_t launch_advance(DevScen*, const int*, int, int, hipStream_t) {
   return hipSuccess;
 }

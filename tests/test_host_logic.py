@@ -271,6 +271,36 @@ def test_link_costs_shape_the_tiles(lib, grid):
     h.close()
 
 
+def test_lane_change_tiles_ordered_only_between_limits(lib):
+    # a graph of the two-kernel step starts with the tile-ordering kernel
+    # exactly when its list holds more lane-change tiles than are resident
+    # at once (6,144) and no more than its eight workgroups, one per XCD,
+    # sort (8 x 2,048); the one-kernel step is never reordered
+    lib.stub_order_nodes.argtypes = [C.POINTER(C.c_int), C.POINTER(C.c_int)]
+    lib.stub_order_nodes.restype = C.c_int
+    last_n, grid = C.c_int(), C.c_int()
+    lc = S.FLAG_LANE_CHANGE | S.FLAG_TURN_LANES
+    regions = set()
+    for scale, flags in ((0.1, lc), (0.35, lc), (0.9, lc), (0.35, 0)):
+        scen = S.portland_like(scale=scale, T=50, depart_max=10, seed=23,
+                               flags=flags)
+        h = Host(lib, max_slots=1, tile_lanes=1, tile_cells=64,
+                 graph_steps=8)  # one link per tile
+        assert h.load_network(0, scen) == sim.OK, h.err()
+        assert h.load_vehicles(0, scen) == sim.OK, h.err()
+        n = h.tiling(0)[1].n_tiles
+        lib.stub_order_nodes(C.byref(last_n), C.byref(grid))
+        assert h.step([0], 8) == sim.OK, h.err()  # one graph of 8 steps
+        k = lib.stub_order_nodes(C.byref(last_n), C.byref(grid))
+        if flags and 6144 < n <= 8 * 2048:
+            assert (k, last_n.value, grid.value) == (1, n, 8), (scale, n)
+        else:
+            assert k == 0, (scale, flags, n)
+        regions.add((bool(flags), (n > 6144) + (n > 8 * 2048)))
+        h.close()
+    assert regions == {(True, 0), (True, 1), (True, 2), (False, 1)}, regions
+
+
 def test_ring_mode_checks(lib):
     h = Host(lib)
     ring = S.ring()
